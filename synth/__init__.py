@@ -1,0 +1,119 @@
+"""Seeded synthetic inputs shared by the HIP path, its tests and the oracle.
+
+This module only draws numbers: it holds none of the solver's arithmetic
+(no matrix, no CG, no stencil, no convolution of the method). Every array
+it returns is a plain numpy array on the host; callers move it where they
+need it.
+
+Recipes (the paper uses no dataset; these stand in for its workloads):
+
+* ``uniform_rhs``: i.i.d. uniform[-1, 1] values in x-fastest order from
+  ``numpy.random.default_rng(seed)`` (PCG64).
+* ``smoothed_rhs``: i.i.d. standard normals from the same generator,
+  smoothed by a separable Gaussian of width ``sigma`` cells (truncated at
+  four sigma, mirror-reflected at the walls), then shifted to zero mean and
+  scaled to unit RMS.  This is the "Gaussian-smoothed random right-hand
+  side" workload.
+* ``net_init``: He-normal initial weights for the warm-start network, one
+  block per layer in tap-major order ``[tap][c_in][c_out]``.
+* ``bf16_values``: random values that are exactly representable in
+  bfloat16, for kernel-level parity checks.
+
+Arrays are indexed ``idx = i + nx * (j + ny * k)`` (x fastest).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "uniform_rhs",
+    "smoothed_rhs",
+    "gaussian_kernel_1d",
+    "net_init",
+    "net_layer_shapes",
+    "bf16_values",
+    "bf16_round_np",
+]
+
+
+def uniform_rhs(n: int | tuple, seed: int) -> np.ndarray:
+    """uniform[-1, 1] values, float64, flat x-fastest array of n^3 (or nx*ny*nz)."""
+    if isinstance(n, int):
+        count = n * n * n
+    else:
+        count = int(np.prod(n))
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=count).astype(np.float64)
+
+
+def gaussian_kernel_1d(sigma: float, truncate: float = 4.0) -> np.ndarray:
+    """Normalised 1-D Gaussian taps of radius ceil(truncate*sigma)."""
+    radius = int(truncate * sigma + 0.5)
+    t = np.arange(-radius, radius + 1, dtype=np.float64)
+    g = np.exp(-0.5 * (t / sigma) ** 2)
+    return g / g.sum()
+
+
+def _smooth_axis(a: np.ndarray, axis: int, taps: np.ndarray) -> np.ndarray:
+    radius = (len(taps) - 1) // 2
+    pad = [(0, 0)] * a.ndim
+    pad[axis] = (radius, radius)
+    # 'symmetric' repeats the edge sample: the mirror about the wall face.
+    ap = np.pad(a, pad, mode="symmetric")
+    out = np.zeros_like(a)
+    n = a.shape[axis]
+    for m, wgt in enumerate(taps):
+        sl = [slice(None)] * a.ndim
+        sl[axis] = slice(m, m + n)
+        out += wgt * ap[tuple(sl)]
+    return out
+
+
+def smoothed_rhs(n: int, seed: int, sigma: float = 3.0) -> np.ndarray:
+    """Zero-mean, unit-RMS Gaussian-smoothed white noise on an n^3 grid (float64, flat)."""
+    rng = np.random.default_rng(seed)
+    white = rng.standard_normal((n, n, n))  # axes (k, j, i): x fastest when flattened
+    taps = gaussian_kernel_1d(sigma)
+    a = white
+    for axis in (2, 1, 0):
+        a = _smooth_axis(a, axis, taps)
+    a = a - a.mean()
+    a = a / np.sqrt(np.mean(a * a))
+    return np.ascontiguousarray(a.reshape(-1))
+
+
+def net_layer_shapes(channels: int = 16, layers: int = 4):
+    """(c_in, c_out) per layer of the warm-start network: 1 -> C -> ... -> C -> 1."""
+    shapes = []
+    for l in range(layers):
+        cin = 1 if l == 0 else channels
+        cout = 1 if l == layers - 1 else channels
+        shapes.append((cin, cout))
+    return shapes
+
+
+def net_init(seed: int, channels: int = 16, layers: int = 4) -> np.ndarray:
+    """He-normal weights, float32, concatenated per layer as [27][c_in][c_out]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in net_layer_shapes(channels, layers):
+        fan_in = 27 * cin
+        w = rng.standard_normal((27, cin, cout)) * np.sqrt(2.0 / fan_in)
+        parts.append(w.astype(np.float32).reshape(-1))
+    return np.concatenate(parts)
+
+
+def bf16_round_np(a: np.ndarray) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even); returns float32."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def bf16_values(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    """float32 array of bfloat16-representable normals (times ``scale``)."""
+    rng = np.random.default_rng(seed)
+    a = (rng.standard_normal(shape) * scale).astype(np.float32)
+    return bf16_round_np(a)

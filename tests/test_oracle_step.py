@@ -1,0 +1,143 @@
+"""Pins of the oracle's fractional time step (staggered grid, Sec. 3.1).
+
+Checks use facts that hold for the method whatever its implementation:
+the projection leaves a discretely divergence-free field (up to the solve
+tolerance), wall-normal faces stay zero, a quiescent cavity stays at rest,
+the cavity is mirror-symmetric in z, semi-Lagrangian advection of a shear
+flow along its own streamlines is the identity, explicit diffusion of a
+quadratic profile adds exactly 2*nu*dt, and the projected divergence obeys
+D_new = D + (dt/(rho h)) * A_neu p.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+
+def shapes(n):
+    return oracle.face_shapes((n, n, n))
+
+
+def u_index(n, i, j, k):
+    return i + (n + 1) * (j + n * k)
+
+
+def test_quiescent_cavity_stays_at_rest():
+    S = oracle.State(8, nu=0.01, lid=0.0)
+    S.p[:] = 0.0
+    for _ in range(3):
+        it, rr, st = oracle.step(S, 0.005)
+        assert st == oracle.OK and it == 0
+    assert not S.u.any() and not S.v.any() and not S.w.any()
+
+
+def _run_cavity(n, steps, nu=0.01, dt=0.005, lid=1.0):
+    S = oracle.State(n, nu=nu, lid=lid)
+    for _ in range(steps):
+        it, rr, st = oracle.step(S, dt, tol=1e-12)
+        assert st == oracle.OK and rr <= 1e-12
+    return S
+
+
+def test_divergence_free_and_walls():
+    n = 10
+    S = _run_cavity(n, 3)
+    D = oracle.divergence(n, S.u, S.v, S.w)
+    # the projection removes the divergence up to the solve tolerance
+    scale = np.abs(S.u).max()
+    assert np.abs(D).max() <= 1e-9 * scale
+    u = S.u.reshape(n, n, n + 1)
+    v = S.v.reshape(n, n + 1, n)
+    w = S.w.reshape(n + 1, n, n)
+    assert not u[:, :, 0].any() and not u[:, :, n].any()
+    assert not v[:, 0, :].any() and not v[:, n, :].any()
+    assert not w[0].any() and not w[n].any()
+    assert np.abs(S.u).max() > 0.01  # the lid did drive a flow
+
+
+def test_z_mirror_symmetry():
+    n = 8
+    S = _run_cavity(n, 3)
+    u = S.u.reshape(n, n, n + 1)
+    v = S.v.reshape(n, n + 1, n)
+    w = S.w.reshape(n + 1, n, n)
+    np.testing.assert_allclose(u, u[::-1], atol=1e-10)
+    np.testing.assert_allclose(v, v[::-1], atol=1e-10)
+    np.testing.assert_allclose(w, -w[::-1], atol=1e-10)
+
+
+def test_advection_of_shear_flow_is_identity():
+    # u = f(y), v = w = 0: back-traces move along x only, where u is constant.
+    n = 10
+    h = 1.0 / n
+    su, sv, sw, _ = shapes(n)
+    y = (np.arange(n) + 0.5) * h
+    u = np.zeros((n, n, n + 1))
+    u[:, :, 1:n] = (0.3 + 0.5 * y)[None, :, None]
+    u = u.reshape(-1)
+    dt = 0.5 * h / 0.8  # departure stays within one cell
+    un, vn, wn = oracle.advect(n, h, 0.0, dt, u, np.zeros(sv), np.zeros(sw))
+    ref = u.reshape(n, n, n + 1)
+    got = un.reshape(n, n, n + 1)
+    np.testing.assert_allclose(got[:, :, 2:n], ref[:, :, 2:n], atol=1e-15)
+    assert not vn.any() and not wn.any()
+
+
+def test_advection_zero_velocity_identity():
+    n = 6
+    h = 1.0 / n
+    su, sv, sw, _ = shapes(n)
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal(su)
+    u.reshape(n, n, n + 1)[:, :, [0, n]] = 0.0
+    un, _, _ = oracle.advect(n, h, 0.0, 0.0, u, np.zeros(sv), np.zeros(sw))
+    # the face position (j + 1/2) h / h - 1/2 is exact only up to rounding
+    np.testing.assert_allclose(un, u, rtol=0, atol=1e-14)
+
+
+def test_diffusion_of_quadratic_profile():
+    n = 10
+    h = 1.0 / n
+    su, sv, sw, _ = shapes(n)
+    y = (np.arange(n) + 0.5) * h
+    u = np.zeros((n, n, n + 1))
+    u[:, :, 1:n] = (y * y)[None, :, None]
+    dt, nu = 1e-3, 0.05
+    un, _, _ = oracle.diffuse(n, h, 0.0, dt, nu, u.reshape(-1), np.zeros(sv), np.zeros(sw))
+    got = un.reshape(n, n, n + 1)
+    # away from the x walls (which are 0 faces) and the y/z walls (ghosts)
+    np.testing.assert_allclose(got[1:n - 1, 1:n - 1, 2:n - 1], (u + 2 * nu * dt)[1:n - 1, 1:n - 1, 2:n - 1],
+                               rtol=0, atol=1e-14)
+
+
+def test_projection_identity():
+    n = 8
+    h = 1.0 / n
+    rho, dt = 1.3, 0.01
+    su, sv, sw, sp = shapes(n)
+    rng = np.random.default_rng(1)
+    u, v, w = rng.standard_normal(su), rng.standard_normal(sv), rng.standard_normal(sw)
+    u.reshape(n, n, n + 1)[:, :, [0, n]] = 0
+    v.reshape(n, n + 1, n)[:, [0, n], :] = 0
+    w.reshape(n + 1, n, n)[[0, n]] = 0
+    p = rng.standard_normal(sp)
+    D = oracle.divergence(n, u, v, w)
+    u2, v2, w2 = oracle.correct(n, h, rho, dt, p, u, v, w)
+    D2 = oracle.divergence(n, u2, v2, w2)
+    Aneu = oracle.assemble(n, -1)
+    np.testing.assert_allclose(D2, D + dt / (rho * h) * oracle.spmv(Aneu, p), atol=1e-12)
+
+
+def test_lid_ghost_sets_tangential_shear():
+    # one step from rest: only the lid drives the flow, through diffusion of
+    # the ghost value 2U - u at the top row; u right below the lid grows by
+    # dt*nu*(2U)/h^2 (advection of a zero field does nothing).
+    n = 8
+    h = 1.0 / n
+    su, sv, sw, _ = shapes(n)
+    dt, nu, U = 1e-3, 0.01, 1.0
+    ua, va, wa = oracle.advect(n, h, U, dt, np.zeros(su), np.zeros(sv), np.zeros(sw))
+    un, _, _ = oracle.diffuse(n, h, U, dt, nu, ua, va, wa)
+    got = un.reshape(n, n, n + 1)
+    np.testing.assert_allclose(got[:, n - 1, 1:n], dt * nu * 2 * U / h**2, rtol=1e-14)
+    assert not got[:, : n - 1, :].any()
