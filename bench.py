@@ -1,0 +1,207 @@
+#!/usr/bin/env python
+"""Benchmark of the pressure-Poisson hot path on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic right-hand side
+at 256^3 (16.8M unknowns, 117M nonzeros): right-hand-side preparation,
+learned warm start (when a trained network is available), and the mixed
+FP32/FP64 reliable-update CG solve to a relative residual of 1e-10.  The
+value is the mean time-to-tolerance per solve.  The same right-hand sides are
+then solved by plain FP64 CG for the comparison factor, and the CG SpMV
+kernel's launches are timed with HIP events for the roofline figure.
+
+Prints ONE JSON line.  --gpus N > 1 is rejected: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def a_kernel_bytes(n, nnz, mixed):
+    """Algorithmic bytes of one launch of the CG SpMV kernel (normal mode).
+
+    CSR: row pointers 4(n+1), columns 4 nnz, values 4 or 8 nnz.
+    Vectors per row: read r, p_old, (d | x), write (d | x), p_new, q.
+    """
+    w = 4 if mixed else 8
+    return 4 * (n + 1) + nnz * (4 + w) + 6 * w * n
+
+
+def spmv_bytes(n, nnz, w):
+    """Plain SpMV y = A x: CSR + x read once + y written once."""
+    return 4 * (n + 1) + nnz * (4 + w) + 2 * w * n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
+    ap.add_argument("--net", default=os.path.join(ROOT, "paper_2504_03697_amd", "weights", "warmstart.npy"))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on a single GPU; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2504_03697_amd as m
+    import synth
+
+    torch.cuda.set_device(0)
+    n = args.n
+    nrows = n ** 3
+    A = m.assemble(n, 0)
+    log(f"assembled {n}^3: n={A.n} nnz={A.nnz}")
+
+    net = None
+    if os.path.exists(args.net):
+        net = m.Net(np.load(args.net))
+        log(f"warm-start network loaded from {args.net}")
+
+    seeds = [1000 + i for i in range(args.warmup + args.steps)]
+    rhs = []
+    for s in seeds:
+        rhs.append(torch.from_numpy(synth.smoothed_rhs(n, s)).cuda())
+    torch.cuda.synchronize()
+    log(f"{len(rhs)} right-hand sides resident in HBM")
+
+    def run(b, precision, use_net):
+        m.rhs_prepare(A, b)
+        x, info = m.solve(A, b, tol=args.tol, precision=precision, net=net if use_net else None, timing=True)
+        return x, info
+
+    for i in range(args.warmup):
+        run(rhs[i], "mixed", True)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for i in range(args.warmup, len(rhs)):
+        _, info = run(rhs[i], "mixed", True)
+        infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log(f"mixed{'+learned' if net else ''}: {ms_per_step:.1f} ms/solve, iters "
+        f"{[i['iters'] for i in infos]}, relres max {max(i['rel_residual'] for i in infos):.2e}")
+
+    fp64 = None
+    if not args.no_fp64:
+        i64 = []
+        t2 = time.perf_counter()
+        for i in range(args.warmup, len(rhs)):
+            _, info = run(rhs[i], "fp64", False)
+            i64.append(info)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        fp64 = {"ms_per_solve": (t3 - t2) * 1e3 / args.steps,
+                "iters": [i["iters"] for i in i64],
+                "rel_residual_max": max(i["rel_residual"] for i in i64),
+                "a_kernel_ms": float(np.mean([i["spmv_ms"] for i in i64 if i["spmv_samples"]]))}
+        log(f"fp64: {fp64['ms_per_solve']:.1f} ms/solve iters {fp64['iters']}")
+
+    # dominant kernel: the mixed-precision CG SpMV kernel, sampled live with
+    # HIP events on the solve stream inside the timed region
+    samples = [(i["spmv_ms"], i["spmv_samples"]) for i in infos if i["spmv_samples"]]
+    a_ms = sum(ms * k for ms, k in samples) / max(1, sum(k for _, k in samples))
+    a_bytes = a_kernel_bytes(A.n, A.nnz, True)
+    achieved = a_bytes / (a_ms * 1e-3) / 1e9 if a_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "cg_a32", "bytes_per_launch": a_bytes, "avg_launch_ms": round(a_ms, 5)}
+
+    # isolated plain SpMV (FP32 values and vectors), 50 back-to-back launches
+    xs = torch.randn(A.n, dtype=torch.float32, device="cuda")
+    ys = torch.empty_like(xs)
+    for _ in range(3):
+        m.spmv(A, xs, ys)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        m.spmv(A, xs, ys)
+    e1.record()
+    torch.cuda.synchronize()
+    spmv_ms = e0.elapsed_time(e1) / 50
+    spmv_gbs = spmv_bytes(A.n, A.nnz, 4) / (spmv_ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n, rhs[args.warmup].cpu().numpy(), fp64["iters"][0] if fp64 else infos[0]["iters"],
+                           args.cpu_seconds)
+
+    value = ms_per_step / 1e3
+    line = {
+        "metric": "Poisson CG time-to-1e-10 & SpMV GB/s, 256^3, plain FP64 vs mixed+learned",
+        "value": round(value, 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"pressure-Poisson CG, {n}^3 pinned Neumann 7-point CSR, Gaussian-smoothed "
+                               f"(sigma=3) random rhs seeds {seeds[args.warmup]}..{seeds[-1]}, tol {args.tol:g}, "
+                               f"mixed FP32/FP64 reliable-update CG" + (" + learned warm start" if net else ""),
+                   "grid": n, "unknowns": A.n, "nnz": A.nnz, "learned_warm_start": net is not None},
+        "iters": [i["iters"] for i in infos],
+        "refreshes": [i["updates"] for i in infos],
+        "rel_residual_max": max(i["rel_residual"] for i in infos),
+        "fp64": fp64,
+        "speedup_vs_fp64": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
+        "spmv_fp32_isolated": {"ms": round(spmv_ms, 5), "gbs": round(spmv_gbs, 1),
+                               "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(n, b, iters_needed, budget_s):
+    """Oracle FP64 CG on the host cores, a bounded number of iterations."""
+    import numpy as np
+
+    import oracle
+    t = time.perf_counter()
+    A = oracle.assemble(n, 0)
+    b = oracle.rhs_prepare(b, 0)
+    log(f"oracle assembled in {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    oracle.cg(A, b, tol=0.0, max_iters=5)
+    t5 = time.perf_counter() - t
+    k = int(max(10, min(2000, budget_s / max(t5 / 5, 1e-6))))
+    t = time.perf_counter()
+    _, it, _, _ = oracle.cg(A, b, tol=0.0, max_iters=k)
+    dt = time.perf_counter() - t
+    per_iter = dt / it
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    log(f"oracle: {it} iterations in {dt:.1f} s on {cores} threads")
+    return {"value": round(per_iter * iters_needed, 3), "unit": "s", "cores": cores, "kind": "oracle",
+            "sample": f"first {it} FP64 CG iterations of one {n}^3 solve ({dt:.1f} s), scaled to the "
+                      f"{iters_needed} iterations plain FP64 CG needs on that right-hand side",
+            "seconds_per_iter": round(per_iter, 5)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * cfdmi.h -- C ABI of the MI355X pressure-Poisson library.
+ *
+ * The library implements the hot path of the lid-driven-cavity proxy app of
+ * arXiv 2504.03697 ("cfdSCOPE"): the pressure-Poisson solve that each
+ * fractional time step performs (Sec. 3.1: the Poisson equation is stored
+ * as a CSR matrix and solved by conjugate gradients; Table 1: spmv, dot and
+ * the vector updates dominate the solver's time), plus the time step that
+ * produces its right-hand side and a learned warm start for the solve.
+ *
+ * Conventions for every function below:
+ *  - Return value: CFD_OK (0) on success, a negative CFD_E* code on failure;
+ *    cfd_last_error() then returns a message (thread-local, valid until the
+ *    next call on that thread).
+ *  - Pointers named as device pointers must point to device memory of the
+ *    current HIP device (for example torch tensors' data_ptr()); the caller
+ *    owns them.  Opaque handles (cfd_csr_t, cfd_net_t) own their device
+ *    workspaces and free them in *_destroy.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All device
+ *    work is enqueued on it.  Functions that return host-side results
+ *    (cfd_solve, cfd_step, cfd_net_train_step) synchronise that stream before
+ *    returning; the others return without synchronising.
+ *  - Grids are nx*ny*nz cubic cells of side h.  Cell arrays are indexed
+ *    idx = i + nx*(j + ny*k) (x fastest).  Face velocities live on the
+ *    staggered grid: u[(nx+1)*ny*nz], v[nx*(ny+1)*nz], w[nx*ny*(nz+1)], each
+ *    indexed x fastest over its own face dimensions.
+ *  - Boundary vectors are float64; float32 and bfloat16 are internal only,
+ *    except in the explicitly typed kernel-level entry points.
+ *  - Results are deterministic: the same inputs on the same device give
+ *    bitwise identical outputs (all reductions run in a fixed order).
+ */
+#ifndef CFDMI_H
+#define CFDMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CFD_OK = 0,
+    CFD_EINVAL = -1,      /* bad argument (sizes, null pointers, options)    */
+    CFD_ENOMEM = -2,      /* device or pinned-host allocation failed          */
+    CFD_EHIP = -3,        /* a HIP runtime call failed                        */
+    CFD_ENOCONV = -4,     /* max_iters reached; x holds the last iterate      */
+    CFD_EBREAKDOWN = -5,  /* p^T A p <= 0: matrix not positive definite       */
+    CFD_ENONFINITE = -6   /* NaN/Inf met in the right-hand side or iteration  */
+};
+
+typedef struct cfd_grid {
+    int32_t nx, ny, nz;   /* cells per direction, each >= 1                   */
+    double h;             /* cell size (unit cube: 1/N)                       */
+} cfd_grid;
+
+/* ------------------------------------------------------------------ */
+/* Matrix (Sec. 3.1 CSR storage; Sec. 3.3: the pattern is fixed)        */
+/* ------------------------------------------------------------------ */
+
+typedef struct cfd_csr *cfd_csr_t;
+
+/*
+ * Assemble, on the device, the 7-point Poisson matrix of the grid in CSR
+ * form (Sec. 3.1).  Values are the integer stencil -h^2*Laplacian with
+ * homogeneous Neumann walls: the diagonal holds the number of in-domain face
+ * neighbours (0..6), each neighbour contributes -1, columns ascend within a
+ * row.  pin >= 0 pins that cell: its row becomes the unit row and its
+ * neighbours' entries in that column are dropped (a symmetric positive
+ * definite matrix); pin < 0 keeps the singular Neumann matrix (valid for
+ * cfd_spmv; cfd_solve rejects it).  Both float64 and float32 value arrays
+ * are stored (the values are small integers, exact in both).
+ * Errors: CFD_EINVAL if a dimension is < 1, pin >= n, or nnz >= 2^31.
+ * The handle is freed with cfd_csr_destroy.
+ */
+int cfd_assemble(const cfd_grid *grid, int64_t pin, void *stream, cfd_csr_t *out);
+
+/* Number of rows (cells) and stored entries. */
+int cfd_csr_info(cfd_csr_t A, int64_t *n, int64_t *nnz);
+
+/*
+ * Copy the CSR arrays into caller-owned device buffers of n+1, nnz and nnz
+ * entries (val receives the float64 values).  Any of the three may be NULL.
+ */
+int cfd_csr_export(cfd_csr_t A, int32_t *row_ptr, int32_t *col, double *val, void *stream);
+
+void cfd_csr_destroy(cfd_csr_t A);
+
+/*
+ * y = A x (Table 1 "spmv") on device vectors of n entries.
+ * precision 0: x, y are double*, float64 values.
+ * precision 1: x, y are float*,  float32 values, float32 accumulation.
+ * x and y must not overlap.
+ */
+int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, void *stream);
+
+/*
+ * Make a right-hand side consistent with the pinned matrix, in place on the
+ * device: subtract its mean (in float64, fixed summation order), then set
+ * b[pin] = 0.  For the singular matrix only the mean is removed.
+ */
+int cfd_rhs_prepare(cfd_csr_t A, double *b, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Solver (Sec. 3.1: conjugate gradients, here unpreconditioned)        */
+/* ------------------------------------------------------------------ */
+
+typedef struct cfd_net *cfd_net_t;
+
+enum { CFD_PREC_FP64 = 0, CFD_PREC_MIXED = 1 };
+
+typedef struct cfd_solve_opts {
+    int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout.
+                            CFD_PREC_MIXED: float32 matrix values, float32
+                            SpMV and vector updates; float64 dot products,
+                            step lengths, solution accumulation and true
+                            residual (reliable-update refinement).          */
+    int32_t max_iters;   /* cap on products q = A p; <= 0 means 100000       */
+    double  ru_delta;    /* mixed only: refresh the float64 residual when the
+                            recursive residual drops below ru_delta times its
+                            maximum since the last refresh; <= 0 means 0.1   */
+    cfd_net_t net;       /* non-NULL: the initial guess is the network's
+                            prediction scaled by the A-optimal factor
+                            (x0 must then be NULL)                           */
+    int32_t chunk;       /* iterations enqueued between host polls; <= 0: 16 */
+    int32_t timing;      /* nonzero: time sampled launches of the CG SpMV
+                            kernel with HIP events (see cfd_solve_info)      */
+} cfd_solve_opts;
+
+typedef struct cfd_solve_info {
+    int32_t iters;          /* products q = A p performed                     */
+    int32_t updates;        /* float64 true-residual refreshes performed      */
+    int32_t status;         /* CFD_OK or the error code returned              */
+    int32_t used_fallback;  /* warm start rejected; zero guess used instead   */
+    double  rel_residual;   /* ||b - A x|| / ||b|| of the returned x (float64) */
+    double  init_residual;  /* ||b - A x0|| / ||b|| of the initial guess       */
+    double  gamma;          /* warm-start scale (0 when not used)             */
+    double  seconds;        /* device time from entry to exit (HIP events)    */
+    double  spmv_ms;        /* mean duration of the sampled CG SpMV launches  */
+    int32_t spmv_samples;   /* number of launches behind spmv_ms              */
+    int32_t pad_;
+} cfd_solve_info;
+
+/*
+ * Solve A x = b for the pinned matrix A to ||b - A x|| <= tol * ||b||
+ * (float64 true residual), starting from x0 (device, may be NULL = zero
+ * guess, may alias x).  b, x0, x: device double[n].  On CFD_ENOCONV,
+ * CFD_EBREAKDOWN and CFD_ENONFINITE, x holds the last iterate and info is
+ * filled.  b = 0 returns x = 0 after 0 iterations.  b must be consistent
+ * (see cfd_rhs_prepare).  Synchronises the stream before returning.
+ */
+int cfd_solve(cfd_csr_t A, const double *b, const double *x0, double tol,
+              const cfd_solve_opts *opts, double *x, cfd_solve_info *info, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Time step (Sec. 3.1 fractional step on the staggered grid)           */
+/* ------------------------------------------------------------------ */
+
+typedef struct cfd_state {
+    cfd_grid grid;
+    double *u, *v, *w;   /* device face velocities (sizes above)             */
+    double *p;           /* device cell pressure, n entries                  */
+    double nu;           /* kinematic viscosity (0 = the paper's Euler model) */
+    double rho;          /* density                                          */
+    double lid_u;        /* speed of the lid: the wall y = ny*h moves in +x   */
+    double gx, gy, gz;   /* constant body force ("applyForces")              */
+    double t;            /* simulated time, advanced by dt                   */
+    int64_t step;        /* step counter, advanced by 1                      */
+    cfd_csr_t A;         /* pinned matrix assembled for `grid`               */
+} cfd_state;
+
+/*
+ * One fractional time step (Sec. 3.1), in place:
+ *  forces (u += dt*g on interior faces) -> semi-Lagrangian advection
+ *  (first-order back-trace, trilinear sampling, departure point clamped to
+ *  the domain) -> explicit viscosity (u += dt*nu*Lap_h u) -> pressure
+ *  correction: D = sum of face-flux differences, b = -(rho*h/dt)*D made
+ *  consistent, A p = b solved from a zero guess to tol with `opts`, then
+ *  interior faces u -= (dt/(rho*h))*(p_right - p_left).
+ * Walls are no-slip; tangential values outside the domain are ghosts
+ * 2*U_wall - inside (U_wall = lid_u for u on the lid, else 0).
+ * Errors: CFD_EINVAL if dt <= 0 or dt*nu*6/h^2 > 1 (explicit viscosity
+ * unstable), plus every cfd_solve error.  Synchronises the stream.
+ */
+int cfd_step(cfd_state *state, double dt, double tol, const cfd_solve_opts *opts,
+             cfd_solve_info *info, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Learned warm start: 3-D convolutional network                        */
+/* ------------------------------------------------------------------ */
+/*
+ * Layers l = 0..L-1: 3x3x3 convolutions with replicate (clamped) padding
+ * and no bias, channels 1 -> C -> ... -> C -> 1, ReLU after all but the
+ * last.  Weights of layer l: [27][c_in][c_out] with tap t = (dz+1)*9 +
+ * (dy+1)*3 + (dx+1); output[v][co] = sum_t sum_ci in[clamp(v+d_t)][ci] *
+ * W[t][ci][co].  Master weights are float32; the forward and backward
+ * passes run in bfloat16 (round to nearest even) with float32 accumulation
+ * on the matrix cores.  Inference normalises by s = rms(b): y = s*f(b/s).
+ */
+
+/* Create a network with C channels (C = 16) and L = 4 layers, weights from
+ * `init` (host float32, cfd_net_param_count values; NULL = all zero). */
+int cfd_net_create(int32_t channels, int32_t layers, const float *init, cfd_net_t *out);
+int64_t cfd_net_param_count(int32_t channels, int32_t layers);
+void cfd_net_destroy(cfd_net_t net);
+
+/* y = s * f(b/s), s = rms(b) (y = 0 when b = 0).  b, y: device double[n]. */
+int cfd_net_forward(cfd_net_t net, const cfd_grid *grid, const double *b, double *y, void *stream);
+
+/*
+ * One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * mean squared error between f(input) and target, averaged over the batch
+ * and the voxels.  input, target: device float[batch*n] (already
+ * normalised).  *loss receives the loss before the update.  Synchronises.
+ */
+int cfd_net_train_step(cfd_net_t net, const cfd_grid *grid, int32_t batch,
+                       const float *input, const float *target, float lr,
+                       float *loss, void *stream);
+
+/* Gradient of that loss w.r.t. the weights at the current weights, without
+ * updating them (host float32 output, cfd_net_param_count values). */
+int cfd_net_gradient(cfd_net_t net, const cfd_grid *grid, int32_t batch,
+                     const float *input, const float *target, float *grad_host,
+                     float *loss, void *stream);
+
+int cfd_net_get_params(cfd_net_t net, float *host_buf, int64_t count);
+int cfd_net_set_params(cfd_net_t net, const float *host_buf, int64_t count);
+
+/*
+ * Kernel-level entry points of one convolution layer (test and tuning use).
+ * x: device bf16 bits (uint16) [n][cin]; w: device bf16 bits [27][cin][cout];
+ * y: device float [n][cout], float32 accumulation, ReLU applied if relu != 0.
+ * cin, cout in {1, 16}.
+ */
+int cfd_conv3d_forward(const cfd_grid *grid, int32_t cin, int32_t cout,
+                       const uint16_t *x, const uint16_t *w, float *y, int32_t relu,
+                       void *stream);
+/* dx[v][ci] = sum over (u, t) with clamp(u + d_t) = v of sum_co dy[u][co] W[t][ci][co]
+ * (the adjoint of cfd_conv3d_forward).  dy: bf16 bits [n][cout]; dx: float [n][cin]. */
+int cfd_conv3d_backward_data(const cfd_grid *grid, int32_t cin, int32_t cout,
+                             const uint16_t *dy, const uint16_t *w, float *dx, void *stream);
+/* dw[t][ci][co] = sum_v x[clamp(v + d_t)][ci] * dy[v][co]; dw: float [27][cin][cout]. */
+int cfd_conv3d_backward_weight(const cfd_grid *grid, int32_t cin, int32_t cout,
+                               const uint16_t *x, const uint16_t *dy, float *dw, void *stream);
+
+const char *cfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CFDMI_H */

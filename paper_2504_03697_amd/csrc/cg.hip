@@ -1,0 +1,823 @@
+// Conjugate-gradient solver (Sec. 3.1 of the paper; Table 1's pcg loop with
+// its spmv, dot and vector updates), device-resident.
+//
+// One iteration is two kernels:
+//   A: fold the pending x update, form the new direction p = r + beta p_old
+//      on the fly while gathering it for q = A p (double-buffered p), write
+//      p, q and the partial sums of p^T q;
+//   B: alpha = rho / p^T q, r -= alpha q, partial sums of r^T r.
+// Every kernel starts by reducing the partial sums of the previous one in a
+// fixed order (every workgroup computes the same bits), so the scalars
+// alpha, beta, the convergence test and the control decisions never leave the
+// device and no atomics or grid barriers are needed.  The control state is
+// double-buffered by launch sequence number: kernel t reads S[t&1] and
+// workgroup 0 writes S[(t+1)&1].
+//
+// A third kernel F ends each chunk of iterations enqueued by the host.  It
+// does nothing unless the iteration asked for a refresh (converged on the
+// recursive residual, reliable-update trigger, iteration cap, breakdown):
+// then it recomputes the true residual b - A x' in float64 for the folded
+// iterate x' gathered on the fly.  The next A kernel writes x' into x and
+// decides: converged, stop with an error, or continue.
+//
+// Mixed precision (reliable updates): the matrix values, r, p, q and the
+// accumulated correction d are float32, normalised by the residual scale s;
+// x, b, the true residual, every dot product and the scalars are float64.
+// When ||r|| falls below ru_delta times its maximum since the last refresh,
+// x' = x + s (d + alpha p) and r64 = b - A x' are formed in float64; the
+// float32 recurrence restarts from r = r64 / ||r64|| keeping the search
+// direction (rescaled into the new units).
+#include "common.h"
+
+#include <hip/hip_ext.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace cfd {
+
+enum Mode : int32_t { MODE_INIT = 0, MODE_NORMAL = 1, MODE_REFRESH = 2 };
+enum Reason : int32_t { R_NONE = 0, R_CONVERGED = 1, R_REFRESH = 2, R_NOCONV = 3, R_BREAKDOWN = 4, R_NONFINITE = 5 };
+
+struct CgState {
+    int32_t done;      // 1 once the solve has finished
+    int32_t status;    // CFD_* code at exit
+    int32_t mode;      // what the next A kernel starts from
+    int32_t pending;   // 1: F must fold x and recompute the true residual
+    int32_t reason;    // why a refresh was requested
+    int32_t iters;     // products q = A p so far
+    int32_t updates;   // refreshes performed
+    int32_t pcur;      // which p buffer holds the current direction
+    int32_t fallback;  // warm start rejected
+    int32_t pad_;
+    double rho;        // r^T r of the residual that generated the current p
+    double rho_new;    // latest recursive r^T r (when a refresh is pending)
+    double alpha;      // step length not yet folded into x (0 = none)
+    double bnorm;      // ||b||
+    double scale;      // s: true residual = s * r (mixed); 1 in float64
+    double rmax;       // max ||r|| since the last refresh (mixed, normalised)
+    double relres;     // last true relative residual
+    double init_relres;
+    double gamma;      // warm-start scale
+};
+
+struct SolveArgs {
+    int64_t n;
+    const int32_t *rp, *col;
+    const double *v64;
+    const float *v32;
+    double tol, ru_delta;
+    int32_t max_iters;
+    int32_t Ga, Gb, Gf;
+    int64_t pin;
+    const double *b;
+    double *x;
+    const double *x0;       // initial guess (NULL = none)
+    const double *y;        // warm-start prediction (NULL = none)
+    double *r, *p0, *p1, *q;          // float64 path (r doubles as r64 in mixed)
+    float *r32, *p32a, *p32b, *q32, *d32;
+    double *partA, *partB, *partF, *partF2, *partG1, *partG2;
+    CgState *S;
+};
+
+struct Workspace {
+    int64_t n = 0;
+    int gmax = 0;
+    double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    float *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *d32 = nullptr;
+    double *y = nullptr;
+    double *part = nullptr;  // 7 * gmax doubles
+    CgState *S = nullptr;
+    CgState *host = nullptr; // pinned, 2 entries
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evc[2] = {nullptr, nullptr};
+    std::vector<hipEvent_t> ta, tb;
+};
+
+void workspace_free(Workspace *ws) {
+    if (!ws) return;
+    double *dd[] = {ws->r, ws->p0, ws->p1, ws->q, ws->y, ws->part};
+    for (double *p : dd) if (p) (void)hipFree(p);
+    float *ff[] = {ws->r32, ws->p32a, ws->p32b, ws->q32, ws->d32};
+    for (float *p : ff) if (p) (void)hipFree(p);
+    if (ws->S) (void)hipFree(ws->S);
+    if (ws->host) (void)hipHostFree(ws->host);
+    hipEvent_t ee[] = {ws->ev0, ws->ev1, ws->evc[0], ws->evc[1]};
+    for (hipEvent_t e : ee) if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ws->ta) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ws->tb) (void)hipEventDestroy(e);
+    delete ws;
+}
+
+template <class T>
+static hipError_t alloc(T **p, int64_t count) {
+    if (*p) return hipSuccess;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)std::max<int64_t>(count, 1));
+}
+
+// Allocate what the requested path needs (kept until cfd_csr_destroy).
+static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm) {
+    if (!A->ws) {
+        A->ws = new Workspace();
+        A->ws->n = A->n;
+        A->ws->gmax = std::max(grid_spmv(A->n), grid_vec(A->n));
+    }
+    Workspace *w = A->ws;
+    const int64_t n = A->n;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = alloc(&w->part, (int64_t)w->gmax * 7);
+    if (e == hipSuccess) e = alloc(&w->S, 2);
+    if (e == hipSuccess && !w->host) e = hipHostMalloc((void **)&w->host, sizeof(CgState) * 2, 0);
+    if (e == hipSuccess) e = alloc(&w->r, n);
+    if (fp64) {
+        if (e == hipSuccess) e = alloc(&w->p0, n);
+        if (e == hipSuccess) e = alloc(&w->p1, n);
+        if (e == hipSuccess) e = alloc(&w->q, n);
+    }
+    if (mixed) {
+        if (e == hipSuccess) e = alloc(&w->r32, n);
+        if (e == hipSuccess) e = alloc(&w->p32a, n);
+        if (e == hipSuccess) e = alloc(&w->p32b, n);
+        if (e == hipSuccess) e = alloc(&w->q32, n);
+        if (e == hipSuccess) e = alloc(&w->d32, n);
+    }
+    if (warm && e == hipSuccess) e = alloc(&w->y, n);
+    if (e == hipSuccess && !w->ev0) e = hipEventCreate(&w->ev0);
+    if (e == hipSuccess && !w->ev1) e = hipEventCreate(&w->ev1);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        if (!w->evc[i]) e = hipEventCreateWithFlags(&w->evc[i], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "solver workspace allocation");
+    return CFD_OK;
+}
+
+double *scratch_partials(cfd_csr_t A) {
+    if (ensure_workspace(A, false, false, false) != CFD_OK) return nullptr;
+    return A->ws->part + 6 * (int64_t)A->ws->gmax;
+}
+
+double *warm_buffer(cfd_csr_t A) {
+    if (ensure_workspace(A, false, false, true) != CFD_OK) return nullptr;
+    return A->ws->y;
+}
+
+// ---------------------------------------------------------------- kernels
+
+#define CG_SHARED(VT)                                  \
+    __shared__ __align__(16) int32_t s_col[kSlab];     \
+    __shared__ __align__(16) VT s_val[kSlab];          \
+    __shared__ double red[kBlock / 64]
+
+__device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// Initial residual r = b - A x0 (x0 = gamma*y for a warm start), x = x0,
+// partial sums of ||r||^2 and ||b||^2; fresh control state.  In mixed mode r
+// is the float64 buffer r64 and d is cleared.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
+    CG_SHARED(double);
+    (void)s_val;
+    __shared__ __align__(16) float s_val32[MIXED ? kSlab : 4];
+    double gamma = 1.0;
+    int fallback = 0;
+    const double *guess = a.x0;
+    if (a.y) {
+        // A-optimal scale of the prediction: gamma = b^T y / y^T A y; zero
+        // guess if it is not finite or y^T A y <= 0.
+        const double yay = reduce_partials(a.partG1, a.Gf, red);
+        const double by = reduce_partials(a.partG2, a.Gf, red);
+        gamma = by / yay;
+        if (!(yay > 0.0) || !std::isfinite(gamma)) {
+            gamma = 0.0;
+            fallback = 1;
+        }
+        guess = gamma != 0.0 ? a.y : nullptr;
+    }
+    const bool have = guess != nullptr;
+    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    double rr = 0.0, bb = 0.0;
+    auto xg = [&](int32_t j) -> double {
+        if (!have) return 0.0;
+        if (a.y) return (j == a.pin) ? 0.0 : gamma * guess[j];
+        return guess[j];
+    };
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * kTileRows;
+        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
+        int rs, re;
+        double acc = 0.0;
+        if constexpr (MIXED) {
+            load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val32, rs, re);
+            if ((int)threadIdx.x < nr && have) acc = row_product<double>(s_col, s_val32, rs, re, xg);
+        } else {
+            load_slab<double>(a.rp, a.col, a.v64, r0, nr, s_col, s_val, rs, re);
+            if ((int)threadIdx.x < nr && have) acc = row_product<double>(s_col, s_val, rs, re, xg);
+        }
+        if ((int)threadIdx.x < nr) {
+            const int64_t i = r0 + threadIdx.x;
+            const double bi = a.b[i];
+            const double ri = bi - acc;
+            a.r[i] = ri;
+            if (a.x != a.x0 || a.y) a.x[i] = xg((int32_t)i);
+            if constexpr (MIXED) a.d32[i] = 0.0f;
+            rr = fma(ri, ri, rr);
+            bb = fma(bi, bi, bb);
+        }
+        __syncthreads();
+    }
+    rr = block_sum(rr, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        a.partF[blockIdx.x] = rr;
+        a.partF2[blockIdx.x] = bb;
+    }
+    if (lead()) {
+        CgState ns{};
+        ns.mode = MODE_INIT;
+        ns.scale = 1.0;
+        ns.gamma = a.y ? gamma : 0.0;
+        ns.fallback = fallback;
+        a.S[(t + 1) & 1] = ns;
+    }
+}
+
+
+// Fold the pending update into x for row i.  The refresh kernel gathers
+// exactly this expression, so the residual it computed is that of the x
+// written here.
+__device__ inline double folded64(const SolveArgs &a, int64_t j, double alpha, const double *p) {
+    return alpha != 0.0 ? fma(alpha, p[j], a.x[j]) : a.x[j];
+}
+__device__ inline double folded32(const SolveArgs &a, int64_t j, double alpha, double s, const float *p) {
+    const double d = alpha != 0.0 ? fma(alpha, (double)p[j], (double)a.d32[j]) : (double)a.d32[j];
+    return fma(s, d, a.x[j]);
+}
+
+// Decision taken at the start of every A kernel from the reduced residual
+// norm.  Identical in every workgroup.
+struct Decision {
+    bool stop;        // no iteration in this kernel
+    bool zero_x;      // b == 0: the answer is x = 0
+    bool fold;        // fold the refreshed update into x (refresh mode)
+    CgState ns;       // state to publish
+    double beta;      // direction coefficient (normal mode)
+    double cref;      // mixed refresh: coefficient on the old direction
+    double inv_s;     // mixed refresh: 1 / new scale
+};
+
+template <bool MIXED>
+__device__ inline Decision decide(const SolveArgs &a, const CgState &st, double *red) {
+    Decision D;
+    D.stop = false;
+    D.zero_x = false;
+    D.fold = false;
+    D.beta = 0.0;
+    D.cref = 0.0;
+    D.inv_s = 1.0;
+    CgState ns = st;
+    if (st.mode == MODE_NORMAL) {
+        const double rr = reduce_partials(a.partB, a.Gb, red);
+        const double nr = sqrt(rr);
+        const double thr = a.tol * st.bnorm;
+        int reason = R_NONE;
+        if (!std::isfinite(rr)) reason = R_NONFINITE;
+        else if (nr * st.scale <= thr) reason = R_CONVERGED;
+        else if (MIXED && nr < a.ru_delta * st.rmax) reason = R_REFRESH;
+        else if (st.iters >= a.max_iters) reason = R_NOCONV;
+        if (reason != R_NONE) {
+            ns.pending = 1;
+            ns.reason = reason;
+            ns.rho_new = rr;
+            D.stop = true;
+        } else {
+            D.beta = rr / st.rho;
+            ns.rho = rr;
+            ns.rmax = std::max(st.rmax, nr);
+        }
+    } else {
+        const double rr = reduce_partials(a.partF, a.Gf, red);
+        if (st.mode == MODE_INIT) {
+            const double bb = reduce_partials(a.partF2, a.Gf, red);
+            ns.bnorm = sqrt(bb);
+        } else {
+            D.fold = true;  // refresh: x += alpha p (or s (d + alpha p))
+        }
+        const double tr = sqrt(rr);
+        const double bn = ns.bnorm;
+        ns.reason = R_NONE;
+        ns.alpha = 0.0;
+        if (!std::isfinite(bn) || !std::isfinite(rr)) {
+            ns.done = 1;
+            ns.status = CFD_ENONFINITE;
+            ns.relres = NAN;
+        } else if (bn == 0.0) {
+            ns.done = 1;
+            ns.status = CFD_OK;
+            ns.relres = 0.0;
+            D.zero_x = true;
+        } else {
+            ns.relres = tr / bn;
+            if (st.mode == MODE_INIT) ns.init_relres = ns.relres;
+            if (tr <= a.tol * bn) {
+                ns.done = 1;
+                ns.status = CFD_OK;
+            } else if (st.reason == R_NOCONV || st.iters >= a.max_iters) {
+                ns.done = 1;
+                ns.status = CFD_ENOCONV;
+            } else if (st.reason == R_BREAKDOWN) {
+                ns.done = 1;
+                ns.status = CFD_EBREAKDOWN;
+            } else if (st.reason == R_NONFINITE) {
+                ns.done = 1;
+                ns.status = CFD_ENONFINITE;
+            }
+        }
+        if (ns.done) {
+            D.stop = true;
+        } else if (MIXED) {
+            // restart the float32 recurrence from r64 / ||r64||, keeping the
+            // old direction (rescaled into the new units) after a refresh:
+            // beta = rho_new / (rho_old (s_old/s_new)^2) with rho_new = 1, and
+            // the rescaled direction p_old * s_old / s_new.
+            D.inv_s = 1.0 / tr;
+            D.cref = (st.mode == MODE_INIT) ? 0.0 : tr / (st.scale * st.rho);
+            ns.scale = tr;
+            ns.rho = 1.0;
+            ns.rmax = 1.0;
+        } else {
+            D.beta = 0.0;  // float64: restart from the true residual
+            ns.rho = rr;
+        }
+    }
+    D.ns = ns;
+    return D;
+}
+
+// A kernel, float64.  Normal: x += alpha p_old; p = r + beta p_old; q = A p.
+// Init/refresh: (fold x) p = r; q = A p.
+__global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
+    CG_SHARED(double);
+    const CgState st = a.S[t & 1];
+    CgState *out = &a.S[(t + 1) & 1];
+    if (st.done || st.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const Decision D = decide<false>(a, st, red);
+    const double *pold = st.pcur ? a.p1 : a.p0;
+    const double alpha = st.alpha;  // pending update (normal mode or refresh fold)
+    if (D.stop) {
+        if (D.zero_x || D.fold)
+            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
+                a.x[i] = D.zero_x ? 0.0 : folded64(a, i, alpha, pold);
+        if (lead()) *out = D.ns;
+        return;
+    }
+    double *pnew = st.pcur ? a.p0 : a.p1;
+    const bool normal = st.mode == MODE_NORMAL;
+    const bool fold = normal || D.fold;
+    const double beta = D.beta;
+    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    double pq = 0.0;
+    auto wg = [&](int32_t j) -> double { return normal ? fma(beta, pold[j], a.r[j]) : a.r[j]; };
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * kTileRows;
+        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
+        int rs, re;
+        load_slab<double>(a.rp, a.col, a.v64, r0, nr, s_col, s_val, rs, re);
+        if ((int)threadIdx.x < nr) {
+            const int64_t i = r0 + threadIdx.x;
+            const double acc = row_product<double>(s_col, s_val, rs, re, wg);
+            const double wi = wg((int32_t)i);
+            if (fold && alpha != 0.0) a.x[i] = folded64(a, i, alpha, pold);
+            pnew[i] = wi;
+            a.q[i] = acc;
+            pq = fma(wi, acc, pq);
+        }
+        __syncthreads();
+    }
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
+    if (lead()) {
+        CgState ns = D.ns;
+        ns.mode = MODE_NORMAL;
+        ns.iters = st.iters + 1;
+        ns.pcur = 1 - st.pcur;
+        ns.alpha = 0.0;
+        *out = ns;
+    }
+}
+
+// A kernel, mixed.  Normal: d += alpha p_old; p = r + beta p_old; q = A p
+// (float32).  Init/refresh: (fold x += s (d + alpha p_old), d = 0)
+// r = r64 / s_new; p = r + cref p_old; q = A p.
+__global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
+    CG_SHARED(float);
+    const CgState st = a.S[t & 1];
+    CgState *out = &a.S[(t + 1) & 1];
+    if (st.done || st.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const Decision D = decide<true>(a, st, red);
+    const float *pold = st.pcur ? a.p32b : a.p32a;
+    const double alpha = st.alpha, s_old = st.scale;
+    if (D.stop) {
+        if (D.zero_x || D.fold)
+            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+                a.x[i] = D.zero_x ? 0.0 : folded32(a, i, alpha, s_old, pold);
+                a.d32[i] = 0.0f;
+            }
+        if (lead()) *out = D.ns;
+        return;
+    }
+    float *pnew = st.pcur ? a.p32a : a.p32b;
+    const bool normal = st.mode == MODE_NORMAL;
+    const bool use_p = normal || st.mode == MODE_REFRESH;
+    const float cf = normal ? (float)D.beta : (float)D.cref;
+    const float af = (float)alpha;
+    const double inv_s = D.inv_s;
+    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    double pq = 0.0;
+    auto rg = [&](int64_t j) -> float { return normal ? a.r32[j] : (float)(a.r[j] * inv_s); };
+    auto wg = [&](int32_t j) -> float { return use_p ? fmaf(cf, pold[j], rg(j)) : rg(j); };
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * kTileRows;
+        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
+        int rs, re;
+        load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val, rs, re);
+        if ((int)threadIdx.x < nr) {
+            const int64_t i = r0 + threadIdx.x;
+            const float acc = row_product<float>(s_col, s_val, rs, re, wg);
+            const float wi = wg((int32_t)i);
+            if (normal) {
+                if (af != 0.0f) a.d32[i] = fmaf(af, pold[i], a.d32[i]);
+            } else {
+                if (D.fold) a.x[i] = folded32(a, i, alpha, s_old, pold);
+                a.d32[i] = 0.0f;
+                a.r32[i] = rg(i);
+            }
+            pnew[i] = wi;
+            a.q32[i] = acc;
+            pq = fma((double)wi, (double)acc, pq);
+        }
+        __syncthreads();
+    }
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
+    if (lead()) {
+        CgState ns = D.ns;
+        ns.mode = MODE_NORMAL;
+        ns.iters = st.iters + 1;
+        ns.pcur = 1 - st.pcur;
+        ns.alpha = 0.0;
+        *out = ns;
+    }
+}
+
+// B kernel: alpha = rho / p^T q; r -= alpha q; partial sums of r^T r.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
+    __shared__ double red[kBlock / 64];
+    const CgState st = a.S[t & 1];
+    CgState *out = &a.S[(t + 1) & 1];
+    if (st.done || st.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const double pq = reduce_partials(a.partA, a.Ga, red);
+    const double alpha = st.rho / pq;
+    if (!(pq > 0.0) || !std::isfinite(alpha)) {
+        if (lead()) {
+            CgState ns = st;
+            ns.pending = 1;
+            ns.reason = R_BREAKDOWN;
+            ns.alpha = 0.0;
+            *out = ns;
+        }
+        return;
+    }
+    double rr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if constexpr (MIXED) {
+        const float af = (float)alpha;
+        const int64_t nv = a.n / 4;
+        float4 *r4 = reinterpret_cast<float4 *>(a.r32);
+        const float4 *q4 = reinterpret_cast<const float4 *>(a.q32);
+        for (int64_t v = first; v < nv; v += stride) {
+            float4 r = r4[v];
+            const float4 q = q4[v];
+            r.x = fmaf(-af, q.x, r.x);
+            r.y = fmaf(-af, q.y, r.y);
+            r.z = fmaf(-af, q.z, r.z);
+            r.w = fmaf(-af, q.w, r.w);
+            r4[v] = r;
+            rr = fma((double)r.x, (double)r.x, rr);
+            rr = fma((double)r.y, (double)r.y, rr);
+            rr = fma((double)r.z, (double)r.z, rr);
+            rr = fma((double)r.w, (double)r.w, rr);
+        }
+        for (int64_t i = nv * 4 + first; i < a.n; i += stride) {
+            const float r = fmaf(-af, a.q32[i], a.r32[i]);
+            a.r32[i] = r;
+            rr = fma((double)r, (double)r, rr);
+        }
+    } else {
+        const int64_t nv = a.n / 2;
+        double2 *r2 = reinterpret_cast<double2 *>(a.r);
+        const double2 *q2 = reinterpret_cast<const double2 *>(a.q);
+        for (int64_t v = first; v < nv; v += stride) {
+            double2 r = r2[v];
+            const double2 q = q2[v];
+            r.x = fma(-alpha, q.x, r.x);
+            r.y = fma(-alpha, q.y, r.y);
+            r2[v] = r;
+            rr = fma(r.x, r.x, rr);
+            rr = fma(r.y, r.y, rr);
+        }
+        for (int64_t i = nv * 2 + first; i < a.n; i += stride) {
+            const double r = fma(-alpha, a.q[i], a.r[i]);
+            a.r[i] = r;
+            rr = fma(r, r, rr);
+        }
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) a.partB[blockIdx.x] = rr;
+    if (lead()) {
+        CgState ns = st;
+        ns.alpha = alpha;
+        *out = ns;
+    }
+}
+
+// F kernel: when a refresh is pending, r = b - A x' in float64 with the
+// folded iterate x' = x + alpha p (float64) or x + s (d + alpha p) (mixed)
+// gathered on the fly.  x itself is only written by the next A kernel (which
+// never gathers x), so no workgroup can see a half-updated x here.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
+    __shared__ __align__(16) int32_t s_col[kSlab];
+    __shared__ __align__(16) double s_val64[MIXED ? 2 : kSlab];
+    __shared__ __align__(16) float s_val32[MIXED ? kSlab : 4];
+    __shared__ double red[kBlock / 64];
+    const CgState st = a.S[t & 1];
+    CgState *out = &a.S[(t + 1) & 1];
+    if (st.done || !st.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const double alpha = st.alpha, s = st.scale;
+    const double *p64 = st.pcur ? a.p1 : a.p0;
+    const float *p32 = st.pcur ? a.p32b : a.p32a;
+    auto xg = [&](int32_t j) -> double {
+        if constexpr (MIXED) return folded32(a, j, alpha, s, p32);
+        else return folded64(a, j, alpha, p64);
+    };
+    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    double rr = 0.0;
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * kTileRows;
+        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
+        int rs, re;
+        double acc = 0.0;
+        if constexpr (MIXED) {
+            load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val32, rs, re);
+            if ((int)threadIdx.x < nr) acc = row_product<double>(s_col, s_val32, rs, re, xg);
+        } else {
+            load_slab<double>(a.rp, a.col, a.v64, r0, nr, s_col, s_val64, rs, re);
+            if ((int)threadIdx.x < nr) acc = row_product<double>(s_col, s_val64, rs, re, xg);
+        }
+        if ((int)threadIdx.x < nr) {
+            const int64_t i = r0 + threadIdx.x;
+            const double ri = a.b[i] - acc;
+            a.r[i] = ri;
+            rr = fma(ri, ri, rr);
+        }
+        __syncthreads();
+    }
+    rr = block_sum(rr, red);
+    if (threadIdx.x == 0) a.partF[blockIdx.x] = rr;
+    if (lead()) {
+        CgState ns = st;
+        ns.pending = 0;
+        ns.mode = MODE_REFRESH;
+        ns.updates = st.updates + 1;
+        *out = ns;
+    }
+}
+
+// Warm start: partial sums of y^T A y and b^T y for gamma, with y[pin] = 0.
+__global__ void __launch_bounds__(kBlock) warm_gamma(SolveArgs a) {
+    __shared__ __align__(16) int32_t s_col[kSlab];
+    __shared__ __align__(16) float s_val[kSlab];
+    __shared__ double red[kBlock / 64];
+    auto yg = [&](int32_t j) -> double { return j == a.pin ? 0.0 : a.y[j]; };
+    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    double yay = 0.0, by = 0.0;
+    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
+        const int64_t r0 = tile * kTileRows;
+        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
+        int rs, re;
+        load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val, rs, re);
+        if ((int)threadIdx.x < nr) {
+            const int64_t i = r0 + threadIdx.x;
+            const double ay = row_product<double>(s_col, s_val, rs, re, yg);
+            const double yi = yg((int32_t)i);
+            yay = fma(yi, ay, yay);
+            by = fma(a.b[i], yi, by);
+        }
+        __syncthreads();
+    }
+    yay = block_sum(yay, red);
+    by = block_sum(by, red);
+    if (threadIdx.x == 0) {
+        a.partG1[blockIdx.x] = yay;
+        a.partG2[blockIdx.x] = by;
+    }
+}
+
+int net_predict(cfd_net_t net, const cfd_grid *grid, const double *b, double *y, hipStream_t s);
+
+// ---------------------------------------------------------------- host driver
+
+static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts *o,
+                      double *x, cfd_solve_info *info, hipStream_t s) {
+    cfd_solve_opts opts{};
+    if (o) opts = *o;
+    const bool mixed = opts.precision == CFD_PREC_MIXED;
+    if (opts.precision != CFD_PREC_FP64 && !mixed) return fail(CFD_EINVAL, "cfd_solve: unknown precision");
+    if (A->pin < 0) return fail(CFD_EINVAL, "cfd_solve: the singular Neumann matrix needs a pinned cell");
+    if (!(tol >= 0.0)) return fail(CFD_EINVAL, "cfd_solve: tol must be >= 0");
+    if (opts.net && x0) return fail(CFD_EINVAL, "cfd_solve: give either x0 or a warm-start network");
+    const int max_iters = opts.max_iters > 0 ? opts.max_iters : 100000;
+    const double delta = opts.ru_delta > 0.0 ? opts.ru_delta : 0.1;
+    const int K = opts.chunk > 0 ? opts.chunk : 16;
+    int rc = ensure_workspace(A, !mixed, mixed, opts.net != nullptr);
+    if (rc != CFD_OK) return rc;
+    Workspace *w = A->ws;
+
+    SolveArgs a{};
+    a.n = A->n;
+    a.rp = A->rp;
+    a.col = A->col;
+    a.v64 = A->val64;
+    a.v32 = A->val32;
+    a.tol = tol;
+    a.ru_delta = delta;
+    a.max_iters = max_iters;
+    a.Ga = grid_spmv(A->n);
+    a.Gb = grid_vec(A->n);
+    a.Gf = grid_spmv(A->n);
+    a.pin = A->pin;
+    a.b = b;
+    a.x = x;
+    a.x0 = x0;
+    a.y = nullptr;
+    a.r = w->r;
+    a.p0 = w->p0;
+    a.p1 = w->p1;
+    a.q = w->q;
+    a.r32 = w->r32;
+    a.p32a = w->p32a;
+    a.p32b = w->p32b;
+    a.q32 = w->q32;
+    a.d32 = w->d32;
+    const int64_t gm = w->gmax;
+    a.partA = w->part;
+    a.partB = w->part + gm;
+    a.partF = w->part + 2 * gm;
+    a.partF2 = w->part + 3 * gm;
+    a.partG1 = w->part + 4 * gm;
+    a.partG2 = w->part + 5 * gm;
+    a.S = w->S;
+
+    CFD_HIP(hipEventRecord(w->ev0, s));
+    if (opts.net) {
+        cfd_grid g{A->nx, A->ny, A->nz, A->h};
+        rc = net_predict(opts.net, &g, b, w->y, s);
+        if (rc != CFD_OK) return rc;
+        a.y = w->y;
+        hipLaunchKernelGGL(warm_gamma, dim3(a.Gf), dim3(kBlock), 0, s, a);
+    }
+    int64_t t = 0;
+    if (mixed) hipLaunchKernelGGL(cg_init<true>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
+    else hipLaunchKernelGGL(cg_init<false>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
+    ++t;
+    CFD_HIP(hipGetLastError());
+
+    // Enqueue chunks of K iterations + one refresh kernel; poll the state of
+    // the previous chunk while the current one runs.
+    const int pool = opts.timing ? 256 : 0;
+    while ((int)w->ta.size() < pool) {
+        hipEvent_t e0, e1;
+        CFD_HIP(hipEventCreate(&e0));
+        CFD_HIP(hipEventCreate(&e1));
+        w->ta.push_back(e0);
+        w->tb.push_back(e1);
+    }
+    std::vector<char> sampled;
+    std::vector<char> live;  // chunk ended with the solve still running
+    const int64_t cap = (int64_t)max_iters + 64;  // every chunk iterates at least once until done
+    int64_t c = 0;
+    bool finished = false;
+    CgState final_state{};
+    for (;; ++c) {
+        if (c > cap) return fail(CFD_EHIP, "cfd_solve: solver control did not terminate");
+        bool smp = false;
+        for (int i = 0; i < K; ++i) {
+            const bool time_it = (i == 1 || K == 1) && c < pool;
+            if (time_it) {
+                smp = true;
+                if (mixed)
+                    hipExtLaunchKernelGGL(cg_a32, dim3(a.Ga), dim3(kBlock), 0, s, w->ta[c], w->tb[c], 0, a, t);
+                else
+                    hipExtLaunchKernelGGL(cg_a64, dim3(a.Ga), dim3(kBlock), 0, s, w->ta[c], w->tb[c], 0, a, t);
+            } else if (mixed) {
+                hipLaunchKernelGGL(cg_a32, dim3(a.Ga), dim3(kBlock), 0, s, a, t);
+            } else {
+                hipLaunchKernelGGL(cg_a64, dim3(a.Ga), dim3(kBlock), 0, s, a, t);
+            }
+            ++t;
+            if (mixed) hipLaunchKernelGGL(cg_b<true>, dim3(a.Gb), dim3(kBlock), 0, s, a, t);
+            else hipLaunchKernelGGL(cg_b<false>, dim3(a.Gb), dim3(kBlock), 0, s, a, t);
+            ++t;
+        }
+        if (mixed) hipLaunchKernelGGL(cg_refresh<true>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
+        else hipLaunchKernelGGL(cg_refresh<false>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
+        ++t;
+        CFD_HIP(hipGetLastError());
+        sampled.push_back(smp);
+        live.push_back(0);
+        const int slot = (int)(c & 1);
+        CFD_HIP(hipMemcpyAsync(&w->host[slot], &w->S[t & 1], sizeof(CgState), hipMemcpyDeviceToHost, s));
+        CFD_HIP(hipEventRecord(w->evc[slot], s));
+        if (c >= 1) {
+            const int prev = (int)((c - 1) & 1);
+            CFD_HIP(hipEventSynchronize(w->evc[prev]));
+            const CgState ps = w->host[prev];
+            live[c - 1] = !ps.done;
+            if (ps.done) {
+                finished = true;
+                break;
+            }
+        }
+    }
+    (void)finished;
+    CFD_HIP(hipEventSynchronize(w->evc[c & 1]));
+    final_state = w->host[c & 1];
+    live[c] = !final_state.done;
+    CFD_HIP(hipEventRecord(w->ev1, s));
+    CFD_HIP(hipEventSynchronize(w->ev1));
+    float ms = 0.0f;
+    CFD_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+
+    cfd_solve_info inf{};
+    inf.iters = final_state.iters;
+    inf.updates = final_state.updates;
+    inf.status = final_state.done ? final_state.status : CFD_EHIP;
+    inf.used_fallback = final_state.fallback;
+    inf.rel_residual = final_state.relres;
+    inf.init_residual = final_state.init_relres;
+    inf.gamma = final_state.gamma;
+    inf.seconds = ms * 1e-3;
+    double tot = 0.0;
+    int ns = 0;
+    for (int64_t i = 0; i < (int64_t)sampled.size() && i < pool; ++i) {
+        if (!sampled[i] || !live[i]) continue;
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, w->ta[i], w->tb[i]) == hipSuccess) {
+            tot += e;
+            ++ns;
+        }
+    }
+    inf.spmv_ms = ns ? tot / ns : 0.0;
+    inf.spmv_samples = ns;
+    if (info) *info = inf;
+    if (!final_state.done) return fail(CFD_EHIP, "cfd_solve: solver did not finish");
+    if (inf.status != CFD_OK) {
+        const char *what = inf.status == CFD_ENOCONV ? "max_iters reached"
+                         : inf.status == CFD_EBREAKDOWN ? "breakdown: p^T A p <= 0"
+                         : inf.status == CFD_ENONFINITE ? "non-finite value in the solve"
+                                                        : "solver error";
+        return fail(inf.status, std::string("cfd_solve: ") + what);
+    }
+    return CFD_OK;
+}
+
+int solve_internal(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts *o,
+                   double *x, cfd_solve_info *info, hipStream_t s) {
+    return solve_impl(A, b, x0, tol, o, x, info, s);
+}
+
+}  // namespace cfd
+
+extern "C" int cfd_solve(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts *opts,
+                         double *x, cfd_solve_info *info, void *stream) {
+    if (!A || !b || !x) return cfd::fail(CFD_EINVAL, "cfd_solve: null argument");
+    return cfd::solve_impl(A, b, x0, tol, opts, x, info, (hipStream_t)stream);
+}

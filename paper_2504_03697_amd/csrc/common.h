@@ -1,0 +1,175 @@
+// Internal declarations shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "cfdmi.h"
+
+namespace cfd {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define CFD_HIP(call)                                     \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return ::cfd::hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------- launch shape
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kTileRows = 256;   // CSR rows per SpMV tile: one row per thread
+constexpr int kMaxRowNnz = 7;    // the 7-point stencil
+constexpr int kXcd = 8;          // MI355X: 8 accelerator complex dies, each with its own L2
+constexpr int kSlab = kTileRows * kMaxRowNnz + 8;  // LDS entries per slab (+ alignment slack)
+constexpr int kPad = 8;          // extra CSR entries allocated past nnz (vector over-read)
+
+struct Device {
+    int id = 0;
+    int cus = 256;
+};
+int device_info(Device *d);
+
+// Grid sizes for the solver's kernels on this device (fixed per device so
+// reductions, which depend on the number of partial sums, are reproducible).
+int grid_spmv(int64_t n);
+int grid_vec(int64_t n);
+
+// ---------------------------------------------------------------- matrix handle
+
+struct Workspace;
+
+}  // namespace cfd
+
+struct cfd_csr {
+    int32_t nx, ny, nz;
+    double h;
+    int64_t n, nnz, pin;
+    int device;
+    int32_t *rp = nullptr;    // n+1
+    int32_t *col = nullptr;   // nnz + kPad
+    double *val64 = nullptr;  // nnz + kPad
+    float *val32 = nullptr;   // nnz + kPad
+    cfd::Workspace *ws = nullptr;
+    void *step_ws = nullptr;  // time-step buffers (step.hip)
+};
+
+namespace cfd {
+
+void workspace_free(Workspace *ws);
+void step_ws_free(void *ws);
+
+// ---------------------------------------------------------------- device helpers
+
+// XCD-aware tile schedule.  Workgroup b is dispatched to XCD b % 8; give each
+// XCD one contiguous range of tiles so the +-nx*ny plane reuse of the SpMV
+// gathers stays inside that XCD's L2.  Falls back to a plain grid-stride loop
+// when the grid is not a multiple of 8.
+struct TileRange {
+    int64_t first, step, end;
+};
+
+__device__ inline TileRange tile_range(int64_t ntiles) {
+    TileRange t;
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G >= kXcd && (G % kXcd) == 0) {
+        const int x = b % kXcd, lb = b / kXcd, bpx = G / kXcd;
+        const int64_t lo = ntiles * x / kXcd, hi = ntiles * (x + 1) / kXcd;
+        t.first = lo + lb;
+        t.step = bpx;
+        t.end = hi;
+    } else {
+        t.first = b;
+        t.step = G;
+        t.end = ntiles;
+    }
+    return t;
+}
+
+// Sum over the 64 lanes of a wavefront; every lane receives the same bits.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup in a fixed order; every thread receives the same
+// bits.  `red` must be __shared__ double[kBlock / 64].
+__device__ inline double block_sum(double v, double *red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// Reduce count partial sums written by the previous kernel, in a fixed order
+// (thread t sums entries t, t+256, ... serially, then block_sum).  Every
+// block of the calling kernel obtains the same bits.
+__device__ inline double reduce_partials(const double *part, int count, double *red) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += kBlock) s += part[i];
+    return block_sum(s, red);
+}
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Stage the CSR slab of rows [r0, r0+nr) in LDS with 16-byte loads.  On
+// return (after a barrier) s_col/s_val hold entries [ea, e1) where ea =
+// row_ptr[r0] rounded down to a multiple of 4; rs/re are this thread's row
+// bounds relative to ea (empty when threadIdx.x >= nr).
+template <class VT>
+__device__ inline void load_slab(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                 const VT *__restrict__ val, int64_t r0, int nr,
+                                 int32_t *s_col, VT *s_val, int &rs, int &re) {
+    const int tid = threadIdx.x;
+    const int32_t e0 = rp[r0], e1 = rp[r0 + nr];
+    const int32_t ea = e0 & ~3;
+    const int cnt = e1 - ea;
+    const i32x4 *c4 = reinterpret_cast<const i32x4 *>(col + ea);
+    for (int v = tid; v * 4 < cnt; v += kBlock)
+        reinterpret_cast<i32x4 *>(s_col)[v] = __builtin_nontemporal_load(c4 + v);
+    if constexpr (sizeof(VT) == 8) {
+        const f64x2 *v2 = reinterpret_cast<const f64x2 *>(val + ea);
+        for (int v = tid; v * 2 < cnt; v += kBlock)
+            reinterpret_cast<f64x2 *>(s_val)[v] = __builtin_nontemporal_load(v2 + v);
+    } else {
+        const f32x4 *v4 = reinterpret_cast<const f32x4 *>(val + ea);
+        for (int v = tid; v * 4 < cnt; v += kBlock)
+            reinterpret_cast<f32x4 *>(s_val)[v] = __builtin_nontemporal_load(v4 + v);
+    }
+    if (tid < nr) {
+        rs = rp[r0 + tid] - ea;
+        re = rp[r0 + tid + 1] - ea;
+    } else {
+        rs = re = 0;
+    }
+    __syncthreads();
+}
+
+// Row product over the staged slab: sum_e val[e] * g(col[e]) in ascending
+// column order.  Rows of the 7-point matrix hold at most 7 entries.
+template <class Acc, class VT, class G>
+__device__ inline Acc row_product(const int32_t *s_col, const VT *s_val, int rs, int re, G &&g) {
+    Acc acc = Acc(0);
+#pragma unroll
+    for (int k = 0; k < kMaxRowNnz; ++k) {
+        const int e = rs + k;
+        if (e < re) acc = fma(Acc(s_val[e]), g(s_col[e]), acc);
+    }
+    return acc;
+}
+
+}  // namespace cfd

@@ -1,0 +1,325 @@
+// Matrix handle: assembly on the device, export, plain SpMV, right-hand-side
+// preparation, and the library's error reporting.
+#include "common.h"
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+
+namespace cfd {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? CFD_ENOMEM : CFD_EHIP;
+}
+
+int device_info(Device *d) {
+    CFD_HIP(hipGetDevice(&d->id));
+    int cus = 0;
+    CFD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->id));
+    d->cus = cus > 0 ? cus : 1;
+    return CFD_OK;
+}
+
+static int g_cus = 0;
+
+static int cus() {
+    if (g_cus == 0) {
+        Device d;
+        if (device_info(&d) == CFD_OK) g_cus = d.cus;
+        else g_cus = 256;
+    }
+    return g_cus;
+}
+
+static int round_grid(int64_t want, int64_t cap) {
+    int64_t g = std::min(want, cap);
+    if (g >= kXcd) g -= g % kXcd;
+    return (int)std::max<int64_t>(g, 1);
+}
+
+// Workgroups for the SpMV-shaped kernels: enough resident waves per CU to
+// keep HBM busy (each workgroup holds ~22 KB of LDS), at most one per tile.
+int grid_spmv(int64_t n) {
+    const int64_t tiles = (n + kTileRows - 1) / kTileRows;
+    return round_grid(tiles, (int64_t)cus() * 6);
+}
+
+// Workgroups for the streaming vector kernels (4 wave64 each).
+int grid_vec(int64_t n) {
+    const int64_t chunks = (n + 4 * kBlock - 1) / (4 * kBlock);
+    return round_grid(chunks, (int64_t)cus() * 4);
+}
+
+// ---------------------------------------------------------------- assembly
+
+// Entries of the unpinned row (i,j,k): 1 + number of in-domain neighbours.
+__host__ __device__ inline int64_t cnt1(int64_t a, int64_t n) {  // neighbours along one axis
+    return (a > 0) + (a < n - 1);
+}
+// sum_{a' < a} cnt1(a', n)
+__host__ __device__ inline int64_t pre1(int64_t a, int64_t n) {
+    return (a > 1 ? a - 1 : 0) + (a < n - 1 ? a : n - 1);
+}
+
+// Start of row (i,j,k) in the unpinned matrix, in closed form: rows are
+// ordered x fastest, so the start is the sum of the lengths of all complete
+// z-planes, y-lines and cells before it.
+__host__ __device__ inline int64_t row_start_unpinned(int64_t i, int64_t j, int64_t k, int64_t nx,
+                                                      int64_t ny, int64_t nz) {
+    const int64_t sx = pre1(nx, nx), sy = pre1(ny, ny);  // 2(n-1) for n >= 1
+    const int64_t cz = cnt1(k, nz), cy = cnt1(j, ny);
+    const int64_t planes = k * (ny * (nx + sx) + nx * sy) + nx * ny * pre1(k, nz);
+    const int64_t lines = j * (nx * (1 + cz) + sx) + nx * pre1(j, ny);
+    const int64_t cells = i * (1 + cy + cz) + pre1(i, nx);
+    return planes + lines + cells;
+}
+
+struct PinInfo {
+    int64_t pin;          // -1: none
+    int64_t nb[6];        // in-domain neighbours of the pin, ascending
+    int nnb;
+    int64_t pin_len;      // unpinned length of the pin row
+};
+
+__host__ __device__ inline int64_t row_start(int64_t row, int64_t i, int64_t j, int64_t k,
+                                             int64_t nx, int64_t ny, int64_t nz, const PinInfo &P) {
+    int64_t s = row_start_unpinned(i, j, k, nx, ny, nz);
+    if (P.pin >= 0) {
+        if (row > P.pin) s -= P.pin_len - 1;           // the pin row keeps one entry
+        for (int q = 0; q < P.nnb; ++q) s -= (P.nb[q] < row);  // each neighbour loses one
+    }
+    return s;
+}
+
+__global__ void __launch_bounds__(kBlock) assemble_kernel(int64_t nx, int64_t ny, int64_t nz,
+                                                          PinInfo P, int32_t *__restrict__ rp,
+                                                          int32_t *__restrict__ col,
+                                                          double *__restrict__ v64,
+                                                          float *__restrict__ v32) {
+    const int64_t n = nx * ny * nz;
+    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row <= n;
+         row += (int64_t)gridDim.x * kBlock) {
+        if (row == n) {
+            rp[n] = (int32_t)row_start(n, 0, 0, nz, nx, ny, nz, P);  // one past the last plane
+            continue;
+        }
+        const int64_t i = row % nx, j = (row / nx) % ny, k = row / (nx * ny);
+        int64_t e = row_start(row, i, j, k, nx, ny, nz, P);
+        rp[row] = (int32_t)e;
+        if (row == P.pin) {
+            col[e] = (int32_t)row;
+            v64[e] = 1.0;
+            v32[e] = 1.0f;
+            continue;
+        }
+        const int64_t deg = cnt1(i, nx) + cnt1(j, ny) + cnt1(k, nz);
+        const int64_t cand[7] = {k > 0 ? row - nx * ny : -1, j > 0 ? row - nx : -1,
+                                 i > 0 ? row - 1 : -1,       row,
+                                 i < nx - 1 ? row + 1 : -1,  j < ny - 1 ? row + nx : -1,
+                                 k < nz - 1 ? row + nx * ny : -1};
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const int64_t c = cand[q];
+            if (c < 0 || c == P.pin) continue;
+            const double a = (c == row) ? (double)deg : -1.0;
+            col[e] = (int32_t)c;
+            v64[e] = a;
+            v32[e] = (float)a;
+            ++e;
+        }
+    }
+}
+
+// Zero the vector over-read padding past nnz so it never holds NaN bits.
+__global__ void pad_kernel(int64_t nnz, int32_t *col, double *v64, float *v32) {
+    const int t = threadIdx.x;
+    if (t < kPad) {
+        col[nnz + t] = 0;
+        v64[nnz + t] = 0.0;
+        v32[nnz + t] = 0.0f;
+    }
+}
+
+}  // namespace cfd
+
+using namespace cfd;
+
+extern "C" int cfd_assemble(const cfd_grid *grid, int64_t pin, void *stream, cfd_csr_t *out) {
+    if (!grid || !out) return fail(CFD_EINVAL, "cfd_assemble: null argument");
+    *out = nullptr;
+    const int64_t nx = grid->nx, ny = grid->ny, nz = grid->nz;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(CFD_EINVAL, "cfd_assemble: grid dimensions must be >= 1");
+    if (!(grid->h > 0.0)) return fail(CFD_EINVAL, "cfd_assemble: h must be > 0");
+    const int64_t n = nx * ny * nz;
+    if (pin >= n) return fail(CFD_EINVAL, "cfd_assemble: pin index out of range");
+    if (pin < 0) pin = -1;
+    PinInfo P{};
+    P.pin = pin;
+    P.nnb = 0;
+    P.pin_len = 0;
+    if (pin >= 0) {
+        const int64_t i = pin % nx, j = (pin / nx) % ny, k = pin / (nx * ny);
+        const int64_t cand[6] = {k > 0 ? pin - nx * ny : -1, j > 0 ? pin - nx : -1,
+                                 i > 0 ? pin - 1 : -1,       i < nx - 1 ? pin + 1 : -1,
+                                 j < ny - 1 ? pin + nx : -1, k < nz - 1 ? pin + nx * ny : -1};
+        for (int q = 0; q < 6; ++q)
+            if (cand[q] >= 0) P.nb[P.nnb++] = cand[q];
+        P.pin_len = 1 + P.nnb;
+    }
+    const int64_t nnz = row_start(n, 0, 0, nz, nx, ny, nz, P);
+    if (n + 1 > INT32_MAX || nnz + kPad > INT32_MAX)
+        return fail(CFD_EINVAL, "cfd_assemble: matrix too large for 32-bit CSR indices");
+
+    cfd_csr *A = new cfd_csr();
+    A->nx = (int32_t)nx;
+    A->ny = (int32_t)ny;
+    A->nz = (int32_t)nz;
+    A->h = grid->h;
+    A->n = n;
+    A->nnz = nnz;
+    A->pin = pin;
+    int rc = CFD_OK;
+    hipError_t e = hipGetDevice(&A->device);
+    if (e == hipSuccess) e = hipMalloc(&A->rp, sizeof(int32_t) * (n + 1));
+    if (e == hipSuccess) e = hipMalloc(&A->col, sizeof(int32_t) * (nnz + kPad));
+    if (e == hipSuccess) e = hipMalloc(&A->val64, sizeof(double) * (nnz + kPad));
+    if (e == hipSuccess) e = hipMalloc(&A->val32, sizeof(float) * (nnz + kPad));
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "cfd_assemble: hipMalloc");
+        cfd_csr_destroy(A);
+        return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t blocks = std::min<int64_t>((n + 1 + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, nx, ny, nz, P,
+                       A->rp, A->col, A->val64, A->val32);
+    hipLaunchKernelGGL(pad_kernel, dim3(1), dim3(64), 0, s, nnz, A->col, A->val64, A->val32);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        rc = hip_fail(e, "cfd_assemble: launch");
+        cfd_csr_destroy(A);
+        return rc;
+    }
+    *out = A;
+    return CFD_OK;
+}
+
+extern "C" int cfd_csr_info(cfd_csr_t A, int64_t *n, int64_t *nnz) {
+    if (!A) return fail(CFD_EINVAL, "cfd_csr_info: null handle");
+    if (n) *n = A->n;
+    if (nnz) *nnz = A->nnz;
+    return CFD_OK;
+}
+
+extern "C" int cfd_csr_export(cfd_csr_t A, int32_t *row_ptr, int32_t *col, double *val, void *stream) {
+    if (!A) return fail(CFD_EINVAL, "cfd_csr_export: null handle");
+    hipStream_t s = (hipStream_t)stream;
+    if (row_ptr)
+        CFD_HIP(hipMemcpyAsync(row_ptr, A->rp, sizeof(int32_t) * (A->n + 1), hipMemcpyDeviceToDevice, s));
+    if (col) CFD_HIP(hipMemcpyAsync(col, A->col, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToDevice, s));
+    if (val) CFD_HIP(hipMemcpyAsync(val, A->val64, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, s));
+    return CFD_OK;
+}
+
+extern "C" void cfd_csr_destroy(cfd_csr_t A) {
+    if (!A) return;
+    if (A->ws) workspace_free(A->ws);
+    if (A->step_ws) step_ws_free(A->step_ws);
+    if (A->rp) (void)hipFree(A->rp);
+    if (A->col) (void)hipFree(A->col);
+    if (A->val64) (void)hipFree(A->val64);
+    if (A->val32) (void)hipFree(A->val32);
+    delete A;
+}
+
+// ---------------------------------------------------------------- plain SpMV
+
+namespace cfd {
+
+template <class VT>
+__global__ void __launch_bounds__(kBlock) spmv_kernel(const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ col,
+                                                      const VT *__restrict__ val, int64_t n,
+                                                      const VT *__restrict__ x, VT *__restrict__ y) {
+    __shared__ __align__(16) int32_t s_col[kSlab];
+    __shared__ __align__(16) VT s_val[kSlab];
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t r0 = t * kTileRows;
+        const int nr = (int)std::min<int64_t>(kTileRows, n - r0);
+        int rs, re;
+        load_slab<VT>(rp, col, val, r0, nr, s_col, s_val, rs, re);
+        if ((int)threadIdx.x < nr) {
+            const VT acc = row_product<VT>(s_col, s_val, rs, re, [&](int j) { return x[j]; });
+            y[r0 + threadIdx.x] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// Partial sums of b for the mean.
+__global__ void __launch_bounds__(kBlock) sum_kernel(const double *__restrict__ b, int64_t n,
+                                                     double *__restrict__ part) {
+    __shared__ double red[kBlock / 64];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = chunk * blockIdx.x, hi = std::min(n, lo + chunk);
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) s += b[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) center_kernel(double *__restrict__ b, int64_t n, int64_t pin,
+                                                        const double *__restrict__ part, int count) {
+    __shared__ double red[kBlock / 64];
+    const double mean = reduce_partials(part, count, red) / (double)n;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        b[i] = (i == pin) ? 0.0 : b[i] - mean;
+}
+
+}  // namespace cfd
+
+extern "C" int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, void *stream) {
+    if (!A || !x || !y) return fail(CFD_EINVAL, "cfd_spmv: null argument");
+    if (precision != CFD_PREC_FP64 && precision != CFD_PREC_MIXED)
+        return fail(CFD_EINVAL, "cfd_spmv: precision must be 0 (float64) or 1 (float32)");
+    hipStream_t s = (hipStream_t)stream;
+    const int G = grid_spmv(A->n);
+    if (precision == CFD_PREC_FP64)
+        hipLaunchKernelGGL(spmv_kernel<double>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val64, A->n,
+                           (const double *)x, (double *)y);
+    else
+        hipLaunchKernelGGL(spmv_kernel<float>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val32, A->n,
+                           (const float *)x, (float *)y);
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+namespace cfd {
+double *scratch_partials(cfd_csr_t A);  // defined with the solver workspace
+}
+
+extern "C" int cfd_rhs_prepare(cfd_csr_t A, double *b, void *stream) {
+    if (!A || !b) return fail(CFD_EINVAL, "cfd_rhs_prepare: null argument");
+    double *part = scratch_partials(A);
+    if (!part) return CFD_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    const int G = grid_vec(A->n);
+    hipLaunchKernelGGL(sum_kernel, dim3(G), dim3(kBlock), 0, s, (const double *)b, A->n, part);
+    hipLaunchKernelGGL(center_kernel, dim3(G), dim3(kBlock), 0, s, b, A->n, A->pin, (const double *)part, G);
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+extern "C" const char *cfd_last_error(void) { return cfd::g_err.c_str(); }

@@ -1,0 +1,744 @@
+// Learned warm start: a small 3-D convolutional network whose forward and
+// backward passes run on the gfx950 matrix cores (bfloat16 operands, float32
+// accumulation).
+//
+// Network: layers l = 0..L-1 of 3x3x3 convolutions with replicate padding
+// and no bias, channels 1 -> 16 -> ... -> 16 -> 1, ReLU after all but the
+// last.  Weights of a layer: W[t][ci][co], t = (dz+1)*9 + (dy+1)*3 + (dx+1).
+// Activations are stored voxel-major with 16 channels contiguous (32 bytes
+// per voxel, bfloat16).
+//
+// Forward (implicit GEMM): for 16 output voxels at a time one wave computes
+// D[co][v] = sum_k A[co][k] B[k][v] with v_mfma_f32_16x16x32_bf16, where
+// k enumerates (tap, input channel) pairs, two taps per 32-wide K step (14
+// steps for 16 input channels, 1 step for the single-channel input layer),
+// A = the layer's weights (pre-packed per lane), and B = the input values at
+// the clamped neighbour of each voxel (a 16-byte gather per lane).  The
+// 16x16 accumulator holds four consecutive channels of one voxel per lane,
+// so the output is written as one 8-byte (bf16) or 16-byte (float) store.
+//
+// Backward data: replicate padding is X_pad[v'] = X[clamp(v')] on the padded
+// grid [-1, n]^3.  Its adjoint is computed in two steps: the same MFMA kernel
+// in "full" mode produces dX_pad[v'] = sum_t dY[v' - d_t] W[t]^T (dY zero
+// outside the grid) over the padded grid, then a fold kernel sums the padded
+// cells that clamp to each voxel.
+//
+// Backward weights: dW[t][ci][co] = sum_v X[clamp(v + d_t)][ci] dY[v][co] is
+// a GEMM with K = voxels; each wave accumulates all 27 taps over its chunks of
+// 32 voxels on the matrix cores and writes one partial sum, which a second
+// kernel reduces in a fixed order (deterministic, no atomics).
+#include "common.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace cfd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kC = 16;  // hidden channels (the matrix-core tile width)
+
+__device__ inline uint16_t f2bf(float f) {
+    const __bf16 h = (__bf16)f;  // round to nearest even
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float bf2f(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+struct Geo {
+    int nx, ny, nz;
+    int64_t n;
+};
+
+__device__ inline int clampi(int a, int lo, int hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+enum ConvMode { FWD = 0, FULL = 1 };
+
+// Source voxel of output o (coordinates i, j, k of the output grid) through
+// tap t, or -1 when it lies outside the input grid (full mode only).
+template <int MODE>
+__device__ inline int64_t conv_src(const Geo &g, int i, int j, int k, int t) {
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    if (MODE == FWD) {
+        const int a = clampi(i + dx, 0, g.nx - 1), b = clampi(j + dy, 0, g.ny - 1), c = clampi(k + dz, 0, g.nz - 1);
+        return (int64_t)a + (int64_t)g.nx * ((int64_t)b + (int64_t)g.ny * c);
+    } else {
+        // output grid is the padded grid: cell (i, j, k) is v' = (i-1, j-1, k-1)
+        const int a = i - 1 - dx, b = j - 1 - dy, c = k - 1 - dz;
+        if (a < 0 || a >= g.nx || b < 0 || b >= g.ny || c < 0 || c >= g.nz) return -1;
+        return (int64_t)a + (int64_t)g.nx * ((int64_t)b + (int64_t)g.ny * c);
+    }
+}
+
+// One convolution on the matrix cores.  CIN/COUT are the channel counts of
+// this convolution (1 or 16); frag holds the packed weights (STEPS x 64 lanes
+// x 8 bfloat16).  Output: float or bfloat16 (with optional ReLU), COUT
+// channels per voxel of the output grid (the input grid, or the padded grid
+// in full mode).
+template <int CIN, int COUT, int MODE, bool OUT_BF16>
+__global__ void __launch_bounds__(kBlock) conv_mfma(Geo g, const uint16_t *__restrict__ in,
+                                                    const u16x8 *__restrict__ frag, void *__restrict__ out,
+                                                    int relu) {
+    constexpr int STEPS = CIN == 16 ? 14 : 1;
+    const int lane = threadIdx.x & 63;
+    const int nl = lane & 15, grp = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    bf16x8 A[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) A[s] = __builtin_bit_cast(bf16x8, frag[s * 64 + lane]);
+    const int ox = g.nx + (MODE == FULL ? 2 : 0), oy = g.ny + (MODE == FULL ? 2 : 0),
+              oz = g.nz + (MODE == FULL ? 2 : 0);
+    const int64_t nout = (int64_t)ox * oy * oz;
+    const int64_t ntiles = (nout + 15) / 16;
+    for (int64_t tile = wave; tile < ntiles; tile += nwaves) {
+        const int64_t o = tile * 16 + nl;
+        const bool valid = o < nout;
+        const int i = (int)(o % ox), j = (int)((o / ox) % oy), k = (int)(o / ((int64_t)ox * oy));
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+            if constexpr (CIN == 16) {
+                const int t = 2 * s + (grp >> 1);
+                const int64_t src = (valid && t < 27) ? conv_src<MODE>(g, i, j, k, t) : -1;
+                if (src >= 0) b = *reinterpret_cast<const u16x8 *>(in + src * 16 + 8 * (grp & 1));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int t = 8 * grp + e;
+                    const int64_t src = (valid && t < 27) ? conv_src<MODE>(g, i, j, k, t) : -1;
+                    if (src >= 0) b[e] = in[src];
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s], __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+        }
+        if (!valid) continue;
+        if (relu) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = acc[q] > 0.f ? acc[q] : 0.f;
+        }
+        if constexpr (COUT == 16) {
+            if constexpr (OUT_BF16) {
+                u16x4 v = {f2bf(acc[0]), f2bf(acc[1]), f2bf(acc[2]), f2bf(acc[3])};
+                *reinterpret_cast<u16x4 *>((uint16_t *)out + o * 16 + 4 * grp) = v;
+            } else {
+                *reinterpret_cast<f32x4 *>((float *)out + o * 16 + 4 * grp) = acc;
+            }
+        } else {
+            if (grp == 0) {
+                if constexpr (OUT_BF16) ((uint16_t *)out)[o] = f2bf(acc[0]);
+                else ((float *)out)[o] = acc[0];
+            }
+        }
+    }
+}
+
+// Pack a layer's float32 weights W[t][cin_f][cout_f] into per-lane MFMA
+// fragments for a convolution with CIN_C input and COUT_C output channels.
+// trans = 0: forward (CIN_C = cin_f); trans = 1: backward data (the
+// convolution maps cout_f channels to cin_f channels).
+template <int CIN_C>
+__global__ void pack_weights(const float *__restrict__ W, int cin_f, int cout_f, int trans, uint16_t *__restrict__ frag) {
+    constexpr int STEPS = CIN_C == 16 ? 14 : 1;
+    const int cin_c = trans ? cout_f : cin_f, cout_c = trans ? cin_f : cout_f;
+    for (int id = blockIdx.x * blockDim.x + threadIdx.x; id < STEPS * 64 * 8; id += gridDim.x * blockDim.x) {
+        const int e = id & 7, lane = (id >> 3) & 63, s = id >> 9;
+        const int grp = lane >> 4, co = lane & 15;
+        int t, ci;
+        if (CIN_C == 16) {
+            t = 2 * s + (grp >> 1);
+            ci = 8 * (grp & 1) + e;
+        } else {
+            t = 8 * grp + e;
+            ci = 0;
+        }
+        float w = 0.f;
+        if (t < 27 && ci < cin_c && co < cout_c)
+            w = trans ? W[((int64_t)t * cin_f + co) * cout_f + ci] : W[((int64_t)t * cin_f + ci) * cout_f + co];
+        frag[id] = f2bf(w);
+    }
+}
+
+// dX[v][c] = sum of dX_pad over the padded cells that clamp to v; optional
+// ReLU mask (act > 0) of the layer input; float or bfloat16 output.
+template <int C, bool MASK, bool OUT_BF16>
+__global__ void __launch_bounds__(kBlock) fold_kernel(Geo g, const float *__restrict__ dxp,
+                                                      const uint16_t *__restrict__ act, void *__restrict__ out) {
+    const int px = g.nx + 2, py = g.ny + 2;
+    for (int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x; id < g.n * C; id += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = id / C;
+        const int c = (int)(id % C);
+        const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((int64_t)g.nx * g.ny));
+        // padded coordinates (+1) that clamp to i: i itself, the low halo if
+        // i == 0, the high halo if i == nx-1
+        int xs[3], ys[3], zs[3], nxs = 0, nys = 0, nzs = 0;
+        xs[nxs++] = i + 1;
+        if (i == 0) xs[nxs++] = 0;
+        if (i == g.nx - 1) xs[nxs++] = g.nx + 1;
+        ys[nys++] = j + 1;
+        if (j == 0) ys[nys++] = 0;
+        if (j == g.ny - 1) ys[nys++] = g.ny + 1;
+        zs[nzs++] = k + 1;
+        if (k == 0) zs[nzs++] = 0;
+        if (k == g.nz - 1) zs[nzs++] = g.nz + 1;
+        float s = 0.f;
+        for (int c3 = 0; c3 < nzs; ++c3)
+            for (int b3 = 0; b3 < nys; ++b3)
+                for (int a3 = 0; a3 < nxs; ++a3)
+                    s += dxp[((int64_t)xs[a3] + (int64_t)px * ((int64_t)ys[b3] + (int64_t)py * zs[c3])) * C + c];
+        if (MASK && !(bf2f(act[id]) > 0.f)) s = 0.f;
+        if (OUT_BF16) ((uint16_t *)out)[id] = f2bf(s);
+        else ((float *)out)[id] = s;
+    }
+}
+
+// Weight gradient partial sums: every wave accumulates dW[t][ci][co] over
+// its chunks of 32 voxels (K = voxels) for all 27 taps.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(kBlock) wgrad_mfma(Geo g, const uint16_t *__restrict__ x,
+                                                     const uint16_t *__restrict__ dy, float *__restrict__ part) {
+    const int lane = threadIdx.x & 63;
+    const int ml = lane & 15, grp = lane >> 4;
+    const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    f32x4 acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int64_t nchunks = (g.n + 31) / 32;
+    for (int64_t ch = wave; ch < nchunks; ch += nwaves) {
+        int vi[8], vj[8], vk[8];
+        bool ok[8];
+        u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t v = ch * 32 + 8 * grp + e;
+            ok[e] = v < g.n;
+            const int64_t vv = ok[e] ? v : 0;
+            vi[e] = (int)(vv % g.nx);
+            vj[e] = (int)((vv / g.nx) % g.ny);
+            vk[e] = (int)(vv / ((int64_t)g.nx * g.ny));
+            if (ok[e] && ml < COUT) b[e] = dy[v * COUT + ml];
+        }
+        const bf16x8 B = __builtin_bit_cast(bf16x8, b);
+#pragma unroll
+        for (int t = 0; t < 27; ++t) {
+            const int dx = t % 3 - 1, dyy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (ml < CIN) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (!ok[e]) continue;
+                    const int64_t src = (int64_t)clampi(vi[e] + dx, 0, g.nx - 1) +
+                                        (int64_t)g.nx * ((int64_t)clampi(vj[e] + dyy, 0, g.ny - 1) +
+                                                         (int64_t)g.ny * clampi(vk[e] + dz, 0, g.nz - 1));
+                    a[e] = x[src * CIN + ml];
+                }
+            }
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), B, acc[t], 0, 0, 0);
+        }
+    }
+    // lane holds D[ci = 4*grp + q][co = lane & 15]
+    float *dst = part + wave * (27 * CIN * COUT);
+#pragma unroll
+    for (int t = 0; t < 27; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ci = 4 * grp + q, co = ml;
+            if (ci < CIN && co < COUT) dst[((int64_t)t * CIN + ci) * COUT + co] = acc[t][q];
+        }
+}
+
+// grad[i] (+)= sum over waves of part[w][i], in wave order.
+__global__ void wgrad_reduce(const float *__restrict__ part, int64_t nwaves, int count, float *__restrict__ grad,
+                             int accumulate) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t w = 0; w < nwaves; ++w) s += part[w * count + i];
+        grad[i] = accumulate ? grad[i] + (float)s : (float)s;
+    }
+}
+
+// Partial sums of squares of a float64 vector (for rms normalisation).
+__global__ void __launch_bounds__(kBlock) sumsq_kernel(const double *__restrict__ b, int64_t n, double *__restrict__ part) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        s = fma(b[i], b[i], s);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// act0 = bf16(b / s), s = rms(b) (0 input when b = 0).
+__global__ void __launch_bounds__(kBlock) net_input_kernel(const double *__restrict__ b, int64_t n,
+                                                           const double *__restrict__ part, int count,
+                                                           uint16_t *__restrict__ act0) {
+    __shared__ double red[kBlock / 64];
+    const double s = sqrt(reduce_partials(part, count, red) / (double)n);
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        act0[i] = f2bf((float)(b[i] * inv));
+}
+
+// y = s * y32.
+__global__ void __launch_bounds__(kBlock) net_output_kernel(const float *__restrict__ y32, int64_t n,
+                                                            const double *__restrict__ part, int count,
+                                                            double *__restrict__ y) {
+    __shared__ double red[kBlock / 64];
+    const double s = sqrt(reduce_partials(part, count, red) / (double)n);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        y[i] = s * (double)y32[i];
+}
+
+__global__ void __launch_bounds__(kBlock) to_bf16_kernel(const float *__restrict__ x, int64_t n, uint16_t *__restrict__ o) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        o[i] = f2bf(x[i]);
+}
+
+__global__ void __launch_bounds__(kBlock) from_bf16_kernel(const uint16_t *__restrict__ x, int64_t n, float *__restrict__ o) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        o[i] = bf2f(x[i]);
+}
+
+// dY = bf16(scale * (y - target)); partial sums of (y - target)^2.
+__global__ void __launch_bounds__(kBlock) loss_grad_kernel(const float *__restrict__ y, const float *__restrict__ tgt,
+                                                           int64_t n, float scale, uint16_t *__restrict__ dy,
+                                                           double *__restrict__ part) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const float d = y[i] - tgt[i];
+        dy[i] = f2bf(scale * d);
+        s = fma((double)d, (double)d, s);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void sum_partials_kernel(const double *__restrict__ part, int count, double *__restrict__ out, int accumulate) {
+    __shared__ double red[kBlock / 64];
+    const double s = reduce_partials(part, count, red);
+    if (threadIdx.x == 0) *out = accumulate ? *out + s : s;
+}
+
+// Adam (Kingma & Ba 2015) on float32 master weights.
+__global__ void adam_kernel(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
+                            const float *__restrict__ gr, int count, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+        const float g = gr[i];
+        const float mi = b1 * m[i] + (1.f - b1) * g;
+        const float vi = b2 * v[i] + (1.f - b2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+static int grid_waves(int64_t work_items_per_wave_units) {
+    Device d;
+    if (device_info(&d) != CFD_OK) d.cus = 256;
+    const int64_t want = (work_items_per_wave_units + 3) / 4;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)d.cus * 8));
+}
+
+template <int CIN, int COUT, int MODE, bool OUT_BF16>
+static void launch_conv(const Geo &g, const uint16_t *in, const uint16_t *frag, void *out, int relu, hipStream_t s) {
+    const int64_t nout = (int64_t)(g.nx + (MODE == FULL ? 2 : 0)) * (g.ny + (MODE == FULL ? 2 : 0)) *
+                         (g.nz + (MODE == FULL ? 2 : 0));
+    const int blocks = grid_waves((nout + 15) / 16);
+    hipLaunchKernelGGL((conv_mfma<CIN, COUT, MODE, OUT_BF16>), dim3(blocks), dim3(kBlock), 0, s, g, in,
+                       (const u16x8 *)frag, out, relu);
+}
+
+static void launch_pack(const float *W, int cin_f, int cout_f, int trans, uint16_t *frag, hipStream_t s) {
+    const int cin_c = trans ? cout_f : cin_f;
+    if (cin_c == 16) hipLaunchKernelGGL(pack_weights<16>, dim3(28), dim3(256), 0, s, W, cin_f, cout_f, trans, frag);
+    else hipLaunchKernelGGL(pack_weights<1>, dim3(2), dim3(256), 0, s, W, cin_f, cout_f, trans, frag);
+}
+
+static int wgrad_waves(int64_t n) {
+    return grid_waves((n + 31) / 32) * 4;  // blocks * 4 waves
+}
+
+template <int CIN, int COUT>
+static void launch_wgrad(const Geo &g, const uint16_t *x, const uint16_t *dy, float *part, float *grad, int accumulate,
+                         hipStream_t s) {
+    const int blocks = grid_waves((g.n + 31) / 32);
+    const int64_t nw = (int64_t)blocks * 4;
+    hipLaunchKernelGGL((wgrad_mfma<CIN, COUT>), dim3(blocks), dim3(kBlock), 0, s, g, x, dy, part);
+    const int count = 27 * CIN * COUT;
+    hipLaunchKernelGGL(wgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, s, (const float *)part, nw, count, grad,
+                       accumulate);
+}
+
+static int frag_elems(int cin_c) { return (cin_c == 16 ? 14 : 1) * 64 * 8; }
+
+}  // namespace cfd
+
+struct cfd_net {
+    int C = 16, L = 4;
+    int64_t count = 0;
+    std::vector<int> cin, cout;
+    std::vector<int64_t> off;        // parameter offset per layer
+    float *theta = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    uint16_t *ffrag = nullptr, *bfrag = nullptr;  // forward / backward-data fragments, 14*64*8 per layer
+    bool dirty = true;
+    int64_t t = 0;                   // Adam step
+    // activation buffers (sized for n)
+    int64_t n = 0, npad = 0;
+    uint16_t *act0 = nullptr;
+    std::vector<uint16_t *> h;       // h[l] = output of layer l (l = 0..L-2), n*16 bf16
+    float *y32 = nullptr;
+    uint16_t *dy = nullptr;          // n bf16
+    uint16_t *dh[2] = {nullptr, nullptr};
+    float *dxp = nullptr;            // padded * 16 float
+    float *wpart = nullptr;
+    int64_t wpart_elems = 0;
+    double *part = nullptr;          // reductions
+    double *loss = nullptr;          // device scalar
+    int gpart = 0;
+};
+
+namespace cfd {
+
+static void net_free_acts(cfd_net *N) {
+    if (N->act0) (void)hipFree(N->act0);
+    for (auto p : N->h) if (p) (void)hipFree(p);
+    N->h.clear();
+    if (N->y32) (void)hipFree(N->y32);
+    if (N->dy) (void)hipFree(N->dy);
+    for (int i = 0; i < 2; ++i) if (N->dh[i]) (void)hipFree(N->dh[i]);
+    if (N->dxp) (void)hipFree(N->dxp);
+    if (N->wpart) (void)hipFree(N->wpart);
+    N->act0 = nullptr;
+    N->y32 = nullptr;
+    N->dy = nullptr;
+    N->dh[0] = N->dh[1] = nullptr;
+    N->dxp = nullptr;
+    N->wpart = nullptr;
+    N->n = 0;
+}
+
+static int net_ensure(cfd_net *N, const Geo &g, bool train) {
+    const int64_t npad = (int64_t)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
+    const bool need_train = train && !N->dxp;
+    if (N->n == g.n && N->npad == npad && !need_train) return CFD_OK;
+    const bool keep_train = train || (N->dxp != nullptr);
+    net_free_acts(N);
+    N->n = g.n;
+    N->npad = npad;
+    CFD_HIP(hipMalloc(&N->act0, sizeof(uint16_t) * g.n));
+    N->h.assign(N->L - 1, nullptr);
+    for (int l = 0; l < N->L - 1; ++l) CFD_HIP(hipMalloc(&N->h[l], sizeof(uint16_t) * g.n * kC));
+    CFD_HIP(hipMalloc(&N->y32, sizeof(float) * g.n));
+    if (keep_train) {
+        CFD_HIP(hipMalloc(&N->dy, sizeof(uint16_t) * g.n));
+        for (int i = 0; i < 2; ++i) CFD_HIP(hipMalloc(&N->dh[i], sizeof(uint16_t) * g.n * kC));
+        CFD_HIP(hipMalloc(&N->dxp, sizeof(float) * npad * kC));
+        N->wpart_elems = (int64_t)wgrad_waves(g.n) * 27 * kC * kC;
+        CFD_HIP(hipMalloc(&N->wpart, sizeof(float) * N->wpart_elems));
+    }
+    return CFD_OK;
+}
+
+static void net_pack(cfd_net *N, hipStream_t s) {
+    if (!N->dirty) return;
+    for (int l = 0; l < N->L; ++l) {
+        launch_pack(N->theta + N->off[l], N->cin[l], N->cout[l], 0, N->ffrag + (int64_t)l * 14 * 64 * 8, s);
+        launch_pack(N->theta + N->off[l], N->cin[l], N->cout[l], 1, N->bfrag + (int64_t)l * 14 * 64 * 8, s);
+    }
+    N->dirty = false;
+}
+
+// Forward pass from the bf16 input act0; layer outputs in h[], final float
+// output in y32.
+static void net_forward_acts(cfd_net *N, const Geo &g, hipStream_t s) {
+    const uint16_t *in = N->act0;
+    for (int l = 0; l < N->L; ++l) {
+        const uint16_t *fr = N->ffrag + (int64_t)l * 14 * 64 * 8;
+        const bool last = l == N->L - 1;
+        if (l == 0) {
+            launch_conv<1, 16, FWD, true>(g, in, fr, N->h[0], 1, s);
+        } else if (!last) {
+            launch_conv<16, 16, FWD, true>(g, in, fr, N->h[l], 1, s);
+        } else {
+            launch_conv<16, 1, FWD, false>(g, in, fr, N->y32, 0, s);
+        }
+        if (!last) in = N->h[l];
+    }
+}
+
+static int grid1(int64_t n) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 4096));
+}
+
+// Backward pass for one sample whose forward activations are in place and
+// whose output gradient (bf16) is in dy; adds the weight gradients to grad.
+static void net_backward(cfd_net *N, const Geo &g, hipStream_t s) {
+    const uint16_t *gout = N->dy;  // gradient w.r.t. the output of layer l
+    int cur = 0;
+    const int gb = grid1(g.n * kC);
+    for (int l = N->L - 1; l >= 0; --l) {
+        const uint16_t *xin = l == 0 ? N->act0 : N->h[l - 1];
+        float *gw = N->grad + N->off[l];
+        const int cin = N->cin[l], cout = N->cout[l];
+        if (cin == 16 && cout == 1) launch_wgrad<16, 1>(g, xin, gout, N->wpart, gw, 1, s);
+        else if (cin == 16) launch_wgrad<16, 16>(g, xin, gout, N->wpart, gw, 1, s);
+        else launch_wgrad<1, 16>(g, xin, gout, N->wpart, gw, 1, s);
+        if (l == 0) break;
+        // dX_pad over the padded grid, then fold with the ReLU mask of h[l-1]
+        const uint16_t *bf = N->bfrag + (int64_t)l * 14 * 64 * 8;
+        if (cout == 1) launch_conv<1, 16, FULL, false>(g, gout, bf, N->dxp, 0, s);
+        else launch_conv<16, 16, FULL, false>(g, gout, bf, N->dxp, 0, s);
+        hipLaunchKernelGGL((fold_kernel<16, true, true>), dim3(gb), dim3(kBlock), 0, s, g, (const float *)N->dxp,
+                           (const uint16_t *)N->h[l - 1], (void *)N->dh[cur]);
+        gout = N->dh[cur];
+        cur ^= 1;
+    }
+}
+
+int net_predict(cfd_net_t N, const cfd_grid *grid, const double *b, double *y, hipStream_t s) {
+    const Geo g{grid->nx, grid->ny, grid->nz, (int64_t)grid->nx * grid->ny * grid->nz};
+    int rc = net_ensure(N, g, false);
+    if (rc != CFD_OK) return rc;
+    net_pack(N, s);
+    const int G = grid1(g.n);
+    hipLaunchKernelGGL(sumsq_kernel, dim3(G), dim3(kBlock), 0, s, b, g.n, N->part);
+    hipLaunchKernelGGL(net_input_kernel, dim3(G), dim3(kBlock), 0, s, b, g.n, (const double *)N->part, G, N->act0);
+    net_forward_acts(N, g, s);
+    hipLaunchKernelGGL(net_output_kernel, dim3(G), dim3(kBlock), 0, s, (const float *)N->y32, g.n,
+                       (const double *)N->part, G, y);
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+static int net_grad_impl(cfd_net_t N, const cfd_grid *grid, int32_t batch, const float *input, const float *target,
+                         float *loss_out, hipStream_t s) {
+    if (!N || !grid || !input || !target || batch < 1) return fail(CFD_EINVAL, "cfd_net: bad argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(CFD_EINVAL, "cfd_net: bad grid");
+    const Geo g{grid->nx, grid->ny, grid->nz, (int64_t)grid->nx * grid->ny * grid->nz};
+    int rc = net_ensure(N, g, true);
+    if (rc != CFD_OK) return rc;
+    net_pack(N, s);
+    CFD_HIP(hipMemsetAsync(N->grad, 0, sizeof(float) * N->count, s));
+    const int G = grid1(g.n);
+    const float scale = 2.0f / (float)((double)batch * (double)g.n);
+    for (int bi = 0; bi < batch; ++bi) {
+        hipLaunchKernelGGL(to_bf16_kernel, dim3(G), dim3(kBlock), 0, s, input + (int64_t)bi * g.n, g.n, N->act0);
+        net_forward_acts(N, g, s);
+        hipLaunchKernelGGL(loss_grad_kernel, dim3(G), dim3(kBlock), 0, s, (const float *)N->y32,
+                           target + (int64_t)bi * g.n, g.n, scale, N->dy, N->part);
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(kBlock), 0, s, (const double *)N->part, G, N->loss,
+                           bi > 0 ? 1 : 0);
+        net_backward(N, g, s);
+    }
+    CFD_HIP(hipGetLastError());
+    double l = 0.0;
+    CFD_HIP(hipMemcpyAsync(&l, N->loss, sizeof(double), hipMemcpyDeviceToHost, s));
+    CFD_HIP(hipStreamSynchronize(s));
+    if (loss_out) *loss_out = (float)(l / ((double)batch * (double)g.n));
+    return CFD_OK;
+}
+
+}  // namespace cfd
+
+using namespace cfd;
+
+extern "C" int64_t cfd_net_param_count(int32_t channels, int32_t layers) {
+    if (channels < 1 || layers < 2) return 0;
+    return 27LL * ((int64_t)channels * 2 + (int64_t)(layers - 2) * channels * channels);
+}
+
+extern "C" int cfd_net_create(int32_t channels, int32_t layers, const float *init, cfd_net_t *out) {
+    if (!out) return fail(CFD_EINVAL, "cfd_net_create: null output");
+    *out = nullptr;
+    if (channels != kC) return fail(CFD_EINVAL, "cfd_net_create: only 16 channels are supported");
+    if (layers < 2 || layers > 16) return fail(CFD_EINVAL, "cfd_net_create: layers must be in [2, 16]");
+    cfd_net *N = new cfd_net();
+    N->C = channels;
+    N->L = layers;
+    int64_t off = 0;
+    for (int l = 0; l < layers; ++l) {
+        const int ci = l == 0 ? 1 : kC, co = l == layers - 1 ? 1 : kC;
+        N->cin.push_back(ci);
+        N->cout.push_back(co);
+        N->off.push_back(off);
+        off += 27LL * ci * co;
+    }
+    N->count = off;
+    hipError_t e = hipMalloc(&N->theta, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc(&N->m, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc(&N->v, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc(&N->grad, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMalloc(&N->ffrag, sizeof(uint16_t) * 14 * 64 * 8 * layers);
+    if (e == hipSuccess) e = hipMalloc(&N->bfrag, sizeof(uint16_t) * 14 * 64 * 8 * layers);
+    if (e == hipSuccess) e = hipMalloc(&N->part, sizeof(double) * 4096);
+    if (e == hipSuccess) e = hipMalloc(&N->loss, sizeof(double));
+    if (e == hipSuccess) e = hipMemset(N->m, 0, sizeof(float) * off);
+    if (e == hipSuccess) e = hipMemset(N->v, 0, sizeof(float) * off);
+    if (e == hipSuccess) e = init ? hipMemcpy(N->theta, init, sizeof(float) * off, hipMemcpyHostToDevice)
+                                  : hipMemset(N->theta, 0, sizeof(float) * off);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        const int rc = hip_fail(e, "cfd_net_create");
+        cfd_net_destroy(N);
+        return rc;
+    }
+    *out = N;
+    return CFD_OK;
+}
+
+extern "C" void cfd_net_destroy(cfd_net_t N) {
+    if (!N) return;
+    net_free_acts(N);
+    float *ff[] = {N->theta, N->m, N->v, N->grad};
+    for (float *p : ff) if (p) (void)hipFree(p);
+    if (N->ffrag) (void)hipFree(N->ffrag);
+    if (N->bfrag) (void)hipFree(N->bfrag);
+    if (N->part) (void)hipFree(N->part);
+    if (N->loss) (void)hipFree(N->loss);
+    delete N;
+}
+
+extern "C" int cfd_net_forward(cfd_net_t N, const cfd_grid *grid, const double *b, double *y, void *stream) {
+    if (!N || !grid || !b || !y) return fail(CFD_EINVAL, "cfd_net_forward: null argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(CFD_EINVAL, "cfd_net_forward: bad grid");
+    return net_predict(N, grid, b, y, (hipStream_t)stream);
+}
+
+extern "C" int cfd_net_gradient(cfd_net_t N, const cfd_grid *grid, int32_t batch, const float *input,
+                                const float *target, float *grad_host, float *loss, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = net_grad_impl(N, grid, batch, input, target, loss, s);
+    if (rc != CFD_OK) return rc;
+    if (grad_host) CFD_HIP(hipMemcpy(grad_host, N->grad, sizeof(float) * N->count, hipMemcpyDeviceToHost));
+    return CFD_OK;
+}
+
+extern "C" int cfd_net_train_step(cfd_net_t N, const cfd_grid *grid, int32_t batch, const float *input,
+                                  const float *target, float lr, float *loss, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    int rc = net_grad_impl(N, grid, batch, input, target, loss, s);
+    if (rc != CFD_OK) return rc;
+    N->t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(b1, (double)N->t)), c2 = (float)(1.0 - std::pow(b2, (double)N->t));
+    hipLaunchKernelGGL(adam_kernel, dim3((N->count + 255) / 256), dim3(256), 0, s, N->theta, N->m, N->v,
+                       (const float *)N->grad, (int)N->count, lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+    CFD_HIP(hipGetLastError());
+    N->dirty = true;
+    CFD_HIP(hipStreamSynchronize(s));
+    return CFD_OK;
+}
+
+extern "C" int cfd_net_get_params(cfd_net_t N, float *host_buf, int64_t count) {
+    if (!N || !host_buf || count != N->count) return fail(CFD_EINVAL, "cfd_net_get_params: bad argument");
+    CFD_HIP(hipDeviceSynchronize());
+    CFD_HIP(hipMemcpy(host_buf, N->theta, sizeof(float) * count, hipMemcpyDeviceToHost));
+    return CFD_OK;
+}
+
+extern "C" int cfd_net_set_params(cfd_net_t N, const float *host_buf, int64_t count) {
+    if (!N || !host_buf || count != N->count) return fail(CFD_EINVAL, "cfd_net_set_params: bad argument");
+    CFD_HIP(hipDeviceSynchronize());
+    CFD_HIP(hipMemcpy(N->theta, host_buf, sizeof(float) * count, hipMemcpyHostToDevice));
+    N->dirty = true;
+    return CFD_OK;
+}
+
+// ---------------------------------------------------------------- kernel-level entry points
+
+static int conv_args(const cfd_grid *grid, int32_t cin, int32_t cout, Geo *g) {
+    if (!grid || grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(CFD_EINVAL, "conv3d: bad grid");
+    if ((cin != 1 && cin != 16) || (cout != 1 && cout != 16) || (cin == 1 && cout == 1))
+        return fail(CFD_EINVAL, "conv3d: channels must be 1 or 16 (not both 1)");
+    *g = Geo{grid->nx, grid->ny, grid->nz, (int64_t)grid->nx * grid->ny * grid->nz};
+    return CFD_OK;
+}
+
+// float32 copy of bf16 weights + packed fragments in one stream-ordered
+// allocation.
+static int conv_weights(const uint16_t *w, int cin, int cout, int trans, hipStream_t s, void **mem, uint16_t **frag) {
+    const int64_t cnt = 27LL * cin * cout;
+    const size_t fbytes = sizeof(uint16_t) * frag_elems(16);
+    CFD_HIP(hipMallocAsync(mem, sizeof(float) * cnt + fbytes, s));
+    float *wf = (float *)*mem;
+    *frag = (uint16_t *)((char *)*mem + sizeof(float) * cnt);
+    hipLaunchKernelGGL(from_bf16_kernel, dim3(grid1(cnt)), dim3(kBlock), 0, s, w, cnt, wf);
+    launch_pack(wf, cin, cout, trans, *frag, s);
+    return CFD_OK;
+}
+
+extern "C" int cfd_conv3d_forward(const cfd_grid *grid, int32_t cin, int32_t cout, const uint16_t *x,
+                                  const uint16_t *w, float *y, int32_t relu, void *stream) {
+    Geo g;
+    int rc = conv_args(grid, cin, cout, &g);
+    if (rc != CFD_OK) return rc;
+    if (!x || !w || !y) return fail(CFD_EINVAL, "conv3d: null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    void *mem;
+    uint16_t *frag;
+    rc = conv_weights(w, cin, cout, 0, s, &mem, &frag);
+    if (rc != CFD_OK) return rc;
+    if (cin == 1) launch_conv<1, 16, FWD, false>(g, x, frag, y, relu, s);
+    else if (cout == 16) launch_conv<16, 16, FWD, false>(g, x, frag, y, relu, s);
+    else launch_conv<16, 1, FWD, false>(g, x, frag, y, relu, s);
+    CFD_HIP(hipFreeAsync(mem, s));
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+extern "C" int cfd_conv3d_backward_data(const cfd_grid *grid, int32_t cin, int32_t cout, const uint16_t *dy,
+                                        const uint16_t *w, float *dx, void *stream) {
+    Geo g;
+    int rc = conv_args(grid, cin, cout, &g);
+    if (rc != CFD_OK) return rc;
+    if (!dy || !w || !dx) return fail(CFD_EINVAL, "conv3d: null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    void *mem;
+    uint16_t *frag;
+    rc = conv_weights(w, cin, cout, 1, s, &mem, &frag);
+    if (rc != CFD_OK) return rc;
+    const int64_t npad = (int64_t)(g.nx + 2) * (g.ny + 2) * (g.nz + 2);
+    float *dxp;
+    CFD_HIP(hipMallocAsync((void **)&dxp, sizeof(float) * npad * cin, s));
+    // this convolution maps cout channels to cin channels
+    if (cout == 1) launch_conv<1, 16, FULL, false>(g, dy, frag, dxp, 0, s);
+    else if (cin == 16) launch_conv<16, 16, FULL, false>(g, dy, frag, dxp, 0, s);
+    else launch_conv<16, 1, FULL, false>(g, dy, frag, dxp, 0, s);
+    const int gb = grid1(g.n * cin);
+    if (cin == 16)
+        hipLaunchKernelGGL((fold_kernel<16, false, false>), dim3(gb), dim3(kBlock), 0, s, g, (const float *)dxp,
+                           (const uint16_t *)nullptr, (void *)dx);
+    else
+        hipLaunchKernelGGL((fold_kernel<1, false, false>), dim3(gb), dim3(kBlock), 0, s, g, (const float *)dxp,
+                           (const uint16_t *)nullptr, (void *)dx);
+    CFD_HIP(hipFreeAsync(dxp, s));
+    CFD_HIP(hipFreeAsync(mem, s));
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+extern "C" int cfd_conv3d_backward_weight(const cfd_grid *grid, int32_t cin, int32_t cout, const uint16_t *x,
+                                          const uint16_t *dy, float *dw, void *stream) {
+    Geo g;
+    int rc = conv_args(grid, cin, cout, &g);
+    if (rc != CFD_OK) return rc;
+    if (!x || !dy || !dw) return fail(CFD_EINVAL, "conv3d: null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nw = wgrad_waves(g.n);
+    float *part;
+    CFD_HIP(hipMallocAsync((void **)&part, sizeof(float) * nw * 27 * cin * cout, s));
+    if (cin == 1) launch_wgrad<1, 16>(g, x, dy, part, dw, 0, s);
+    else if (cout == 16) launch_wgrad<16, 16>(g, x, dy, part, dw, 0, s);
+    else launch_wgrad<16, 1>(g, x, dy, part, dw, 0, s);
+    CFD_HIP(hipFreeAsync(part, s));
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}

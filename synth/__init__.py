@@ -55,18 +55,9 @@ def gaussian_kernel_1d(sigma: float, truncate: float = 4.0) -> np.ndarray:
 
 
 def _smooth_axis(a: np.ndarray, axis: int, taps: np.ndarray) -> np.ndarray:
-    radius = (len(taps) - 1) // 2
-    pad = [(0, 0)] * a.ndim
-    pad[axis] = (radius, radius)
-    # 'symmetric' repeats the edge sample: the mirror about the wall face.
-    ap = np.pad(a, pad, mode="symmetric")
-    out = np.zeros_like(a)
-    n = a.shape[axis]
-    for m, wgt in enumerate(taps):
-        sl = [slice(None)] * a.ndim
-        sl[axis] = slice(m, m + n)
-        out += wgt * ap[tuple(sl)]
-    return out
+    from scipy.ndimage import correlate1d
+    # mode 'reflect' repeats the edge sample: the mirror about the wall face.
+    return correlate1d(a, taps, axis=axis, mode="reflect")
 
 
 def smoothed_rhs(n: int, seed: int, sigma: float = 3.0) -> np.ndarray:
