@@ -107,6 +107,7 @@ int cfd_rhs_prepare(cfd_csr_t A, double *b, void *stream);
 typedef struct cfd_net *cfd_net_t;
 
 enum { CFD_PREC_FP64 = 0, CFD_PREC_MIXED = 1 };
+enum { CFD_FORM_PINNED = 0, CFD_FORM_PROJECTED = 1 };
 
 typedef struct cfd_solve_opts {
     int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout.
@@ -124,6 +125,15 @@ typedef struct cfd_solve_opts {
     int32_t chunk;       /* iterations enqueued between host polls; <= 0: 16 */
     int32_t timing;      /* nonzero: time sampled launches of the CG SpMV
                             kernel with HIP events (see cfd_solve_info)      */
+    int32_t formulation; /* CFD_FORM_PINNED: CG on the stored pinned matrix.
+                            CFD_FORM_PROJECTED: CG on the consistent Neumann
+                            system A_neu x = c (c_i = b_i - b_pin for the
+                            pin's neighbours, c_pin = -sum of the others),
+                            whose solutions differ from the pinned solution
+                            by a constant; x is shifted so x_pin = b_pin.
+                            Same answer, without the pinned cell's isolated
+                            small eigenvalue.                                */
+    int32_t reserved_;
 } cfd_solve_opts;
 
 typedef struct cfd_solve_info {

@@ -21,6 +21,7 @@ from . import _lib
 from ._lib import CfdError, CfdGrid, CfdSolveInfo, CfdSolveOpts, CfdState, check, load
 
 PREC = {"fp64": 0, "mixed": 1}
+FORM = {"pinned": 0, "projected": 1}
 
 
 def _torch():
@@ -117,18 +118,19 @@ def rhs_prepare(A: Csr, b):
     return b
 
 
-def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False):
+def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned"):
     return CfdSolveOpts(PREC[precision] if isinstance(precision, str) else int(precision), int(max_iters),
-                        float(ru_delta), net.handle if net is not None else None, int(chunk), int(bool(timing)))
+                        float(ru_delta), net.handle if net is not None else None, int(chunk), int(bool(timing)),
+                        FORM[formulation] if isinstance(formulation, str) else int(formulation), 0)
 
 
 def solve(A: Csr, b, x0=None, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0,
-          chunk=0, timing=False, x=None, raise_on_error=True):
+          chunk=0, timing=False, x=None, raise_on_error=True, formulation="pinned"):
     """Solve A x = b on the device.  Returns (x, info dict)."""
     torch = _torch()
     if x is None:
         x = torch.empty(A.n, dtype=torch.float64, device=b.device)
-    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing)
+    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing, formulation)
     info = CfdSolveInfo()
     rc = load().cfd_solve(A.handle, _ptr(b, torch.float64, A.n, "b"), _ptr(x0, torch.float64, A.n, "x0"),
                           float(tol), ctypes.byref(opts), _ptr(x, torch.float64, A.n, "x"),
@@ -166,8 +168,9 @@ class State:
         return self.c.step
 
 
-def step(S: State, dt, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0, chunk=0):
-    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, False)
+def step(S: State, dt, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0, chunk=0,
+         formulation="pinned"):
+    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, False, formulation)
     info = CfdSolveInfo()
     check(load().cfd_step(ctypes.byref(S.c), float(dt), float(tol), ctypes.byref(opts), ctypes.byref(info),
                           _stream()))

@@ -60,6 +60,7 @@ struct CgState {
     double relres;     // last true relative residual
     double init_relres;
     double gamma;      // warm-start scale
+    double xpin;       // folded iterate at the pinned cell (projected formulation)
 };
 
 struct SolveArgs {
@@ -71,13 +72,18 @@ struct SolveArgs {
     int32_t max_iters;
     int32_t Ga, Gb, Gf;
     int64_t pin;
-    const double *b;
+    int32_t proj;           // 1: CG on the consistent Neumann system, shifted at exit
+    int32_t nnb;            // in-domain neighbours of the pinned cell
+    int64_t nb[6];
+    int64_t nxny;
+    const double *b;        // right-hand side of the pinned system
+    double *c;              // consistent Neumann right-hand side (projected), else b
     double *x;
     const double *x0;       // initial guess (NULL = none)
     const double *y;        // warm-start prediction (NULL = none)
     double *r, *p0, *p1, *q;          // float64 path (r doubles as r64 in mixed)
     float *r32, *p32a, *p32b, *q32, *d32;
-    double *partA, *partB, *partF, *partF2, *partG1, *partG2;
+    double *partA, *partB, *partF, *partF2, *partG1, *partG2, *partFp, *partS;
     CgState *S;
 };
 
@@ -87,7 +93,8 @@ struct Workspace {
     double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     float *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *d32 = nullptr;
     double *y = nullptr;
-    double *part = nullptr;  // 7 * gmax doubles
+    double *c = nullptr;     // consistent right-hand side (projected formulation)
+    double *part = nullptr;  // 9 * gmax doubles
     CgState *S = nullptr;
     CgState *host = nullptr; // pinned, 2 entries
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evc[2] = {nullptr, nullptr};
@@ -96,7 +103,7 @@ struct Workspace {
 
 void workspace_free(Workspace *ws) {
     if (!ws) return;
-    double *dd[] = {ws->r, ws->p0, ws->p1, ws->q, ws->y, ws->part};
+    double *dd[] = {ws->r, ws->p0, ws->p1, ws->q, ws->y, ws->c, ws->part};
     for (double *p : dd) if (p) (void)hipFree(p);
     float *ff[] = {ws->r32, ws->p32a, ws->p32b, ws->q32, ws->d32};
     for (float *p : ff) if (p) (void)hipFree(p);
@@ -116,16 +123,16 @@ static hipError_t alloc(T **p, int64_t count) {
 }
 
 // Allocate what the requested path needs (kept until cfd_csr_destroy).
-static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm) {
+static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm, bool proj = false) {
     if (!A->ws) {
         A->ws = new Workspace();
         A->ws->n = A->n;
-        A->ws->gmax = std::max(grid_spmv(A->n), grid_vec(A->n));
+        A->ws->gmax = std::max(grid_spmv(A->n, 4), grid_vec(A->n));
     }
     Workspace *w = A->ws;
     const int64_t n = A->n;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = alloc(&w->part, (int64_t)w->gmax * 7);
+    if (e == hipSuccess) e = alloc(&w->part, (int64_t)w->gmax * 9);
     if (e == hipSuccess) e = alloc(&w->S, 2);
     if (e == hipSuccess && !w->host) e = hipHostMalloc((void **)&w->host, sizeof(CgState) * 2, 0);
     if (e == hipSuccess) e = alloc(&w->r, n);
@@ -142,6 +149,7 @@ static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm) {
         if (e == hipSuccess) e = alloc(&w->d32, n);
     }
     if (warm && e == hipSuccess) e = alloc(&w->y, n);
+    if (proj && e == hipSuccess) e = alloc(&w->c, n);
     if (e == hipSuccess && !w->ev0) e = hipEventCreate(&w->ev0);
     if (e == hipSuccess && !w->ev1) e = hipEventCreate(&w->ev1);
     for (int i = 0; i < 2 && e == hipSuccess; ++i)
@@ -163,25 +171,55 @@ double *warm_buffer(cfd_csr_t A) {
 // ---------------------------------------------------------------- kernels
 
 #define CG_SHARED(VT)                                  \
-    __shared__ __align__(16) int32_t s_col[kSlab];     \
-    __shared__ __align__(16) VT s_val[kSlab];          \
+    __shared__ __align__(16) int32_t s_col[kSlabLds];  \
+    __shared__ __align__(16) VT s_val[kSlabLds];       \
     __shared__ double red[kBlock / 64]
 
 __device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
-// Initial residual r = b - A x0 (x0 = gamma*y for a warm start), x = x0,
-// partial sums of ||r||^2 and ||b||^2; fresh control state.  In mixed mode r
-// is the float64 buffer r64 and d is cleared.
+// Projected formulation.  The stored matrix is the pinned one, A_pin; the
+// Neumann matrix differs from it only in the pinned row (which becomes
+// deg*e_pin - sum of its neighbours) and in the pinned column (-1 in each
+// neighbour row).  Row i of A_neu w is therefore row i of A_pin w plus this
+// correction (nonzero in at most 7 rows).
+template <class T, class G>
+__device__ inline T neu_fix(const SolveArgs &a, int64_t i, T acc, G &&g) {
+    if (!a.proj) return acc;
+    const int64_t d = i - a.pin;
+    if (d > a.nxny || d < -a.nxny) return acc;
+    if (d == 0) {
+        T s = (T)(a.nnb - 1) * g((int32_t)a.pin);
+        for (int q = 0; q < a.nnb; ++q) s -= g((int32_t)a.nb[q]);
+        return acc + s;
+    }
+    for (int q = 0; q < a.nnb; ++q)
+        if (i == a.nb[q]) return acc - g((int32_t)a.pin);
+    return acc;
+}
+
+__device__ inline bool is_pin_nb(const SolveArgs &a, int64_t i) {
+    for (int q = 0; q < a.nnb; ++q)
+        if (i == a.nb[q]) return true;
+    return false;
+}
+
+// Initial residual r = c - A x0 (x0 = gamma*y for a warm start), x = x0,
+// partial sums of ||r||^2 (full and without the pinned row) and ||b||^2;
+// fresh control state.  In mixed mode r is the float64 buffer r64 and d is
+// cleared.  Projected formulation: the consistent Neumann right-hand side is
+// c_i = b_i - b_pin [i neighbours the pin], c_pin = -sum_{i != pin} c_i, so
+// that A_neu x = c with x_pin = b_pin is the pinned solution.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
-    CG_SHARED(double);
-    (void)s_val;
-    __shared__ __align__(16) float s_val32[MIXED ? kSlab : 4];
+    typedef typename std::conditional<MIXED, float, double>::type VT;
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) VT s_val[kSlabLds];
+    __shared__ double red[kBlock / 64];
     double gamma = 1.0;
     int fallback = 0;
     const double *guess = a.x0;
     if (a.y) {
-        // A-optimal scale of the prediction: gamma = b^T y / y^T A y; zero
+        // A-optimal scale of the prediction: gamma = c^T y / y^T A y; zero
         // guess if it is not finite or y^T A y <= 0.
         const double yay = reduce_partials(a.partG1, a.Gf, red);
         const double by = reduce_partials(a.partG2, a.Gf, red);
@@ -192,43 +230,43 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
         }
         guess = gamma != 0.0 ? a.y : nullptr;
     }
+    const double bpin = a.b[a.pin];
+    double cpin = bpin;
+    if (a.proj) {
+        const double sb = reduce_partials(a.partS, a.Gb, red);
+        cpin = -(sb - bpin) + (double)a.nnb * bpin;
+    }
     const bool have = guess != nullptr;
-    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
-    double rr = 0.0, bb = 0.0;
+    double rr = 0.0, rp = 0.0, bb = 0.0;
     auto xg = [&](int32_t j) -> double {
         if (!have) return 0.0;
         if (a.y) return (j == a.pin) ? 0.0 : gamma * guess[j];
         return guess[j];
     };
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-        const int64_t r0 = tile * kTileRows;
-        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
-        int rs, re;
+    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
+    csr_sweep<VT>(a.rp, a.col, val, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
         double acc = 0.0;
-        if constexpr (MIXED) {
-            load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val32, rs, re);
-            if ((int)threadIdx.x < nr && have) acc = row_product<double>(s_col, s_val32, rs, re, xg);
-        } else {
-            load_slab<double>(a.rp, a.col, a.v64, r0, nr, s_col, s_val, rs, re);
-            if ((int)threadIdx.x < nr && have) acc = row_product<double>(s_col, s_val, rs, re, xg);
+        if (have) acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, xg), xg);
+        const double bi = a.b[i];
+        double ci = bi;
+        if (a.proj) {
+            ci = (i == a.pin) ? cpin : (is_pin_nb(a, i) ? bi - bpin : bi);
+            a.c[i] = ci;
         }
-        if ((int)threadIdx.x < nr) {
-            const int64_t i = r0 + threadIdx.x;
-            const double bi = a.b[i];
-            const double ri = bi - acc;
-            a.r[i] = ri;
-            if (a.x != a.x0 || a.y) a.x[i] = xg((int32_t)i);
-            if constexpr (MIXED) a.d32[i] = 0.0f;
-            rr = fma(ri, ri, rr);
-            bb = fma(bi, bi, bb);
-        }
-        __syncthreads();
-    }
+        const double ri = ci - acc;
+        a.r[i] = ri;
+        if (a.x != a.x0 || a.y) a.x[i] = xg((int32_t)i);
+        if constexpr (MIXED) a.d32[i] = 0.0f;
+        rr = fma(ri, ri, rr);
+        if (!(a.proj && i == a.pin)) rp = fma(ri, ri, rp);
+        bb = fma(bi, bi, bb);
+    });
     rr = block_sum(rr, red);
+    rp = block_sum(rp, red);
     bb = block_sum(bb, red);
     if (threadIdx.x == 0) {
         a.partF[blockIdx.x] = rr;
+        a.partFp[blockIdx.x] = rp;
         a.partF2[blockIdx.x] = bb;
     }
     if (lead()) {
@@ -237,10 +275,10 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
         ns.scale = 1.0;
         ns.gamma = a.y ? gamma : 0.0;
         ns.fallback = fallback;
+        ns.xpin = xg((int32_t)a.pin);
         a.S[(t + 1) & 1] = ns;
     }
 }
-
 
 // Fold the pending update into x for row i.  The refresh kernel gathers
 // exactly this expression, so the residual it computed is that of the x
@@ -263,6 +301,7 @@ struct Decision {
     double beta;      // direction coefficient (normal mode)
     double cref;      // mixed refresh: coefficient on the old direction
     double inv_s;     // mixed refresh: 1 / new scale
+    double shift;     // projected formulation, final x: + (b_pin - x_pin)
 };
 
 template <bool MIXED>
@@ -274,6 +313,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     D.beta = 0.0;
     D.cref = 0.0;
     D.inv_s = 1.0;
+    D.shift = 0.0;
     CgState ns = st;
     if (st.mode == MODE_NORMAL) {
         const double rr = reduce_partials(a.partB, a.Gb, red);
@@ -295,18 +335,21 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
             ns.rmax = std::max(st.rmax, nr);
         }
     } else {
+        // rr: ||r||^2 of the system being iterated; rrp: ||r||^2 of the pinned
+        // system at the (shifted) iterate, which decides convergence
         const double rr = reduce_partials(a.partF, a.Gf, red);
+        const double rrp = reduce_partials(a.partFp, a.Gf, red);
         if (st.mode == MODE_INIT) {
             const double bb = reduce_partials(a.partF2, a.Gf, red);
             ns.bnorm = sqrt(bb);
         } else {
             D.fold = true;  // refresh: x += alpha p (or s (d + alpha p))
         }
-        const double tr = sqrt(rr);
+        const double tr = sqrt(rr), trp = sqrt(rrp);
         const double bn = ns.bnorm;
         ns.reason = R_NONE;
         ns.alpha = 0.0;
-        if (!std::isfinite(bn) || !std::isfinite(rr)) {
+        if (!std::isfinite(bn) || !std::isfinite(rr) || !std::isfinite(rrp)) {
             ns.done = 1;
             ns.status = CFD_ENONFINITE;
             ns.relres = NAN;
@@ -316,9 +359,9 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
             ns.relres = 0.0;
             D.zero_x = true;
         } else {
-            ns.relres = tr / bn;
+            ns.relres = trp / bn;
             if (st.mode == MODE_INIT) ns.init_relres = ns.relres;
-            if (tr <= a.tol * bn) {
+            if (trp <= a.tol * bn) {
                 ns.done = 1;
                 ns.status = CFD_OK;
             } else if (st.reason == R_NOCONV || st.iters >= a.max_iters) {
@@ -334,6 +377,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
         }
         if (ns.done) {
             D.stop = true;
+            if (a.proj && !D.zero_x) D.shift = a.b[a.pin] - st.xpin;
         } else if (MIXED) {
             // restart the float32 recurrence from r64 / ||r64||, keeping the
             // old direction (rescaled into the new units) after a refresh:
@@ -367,9 +411,11 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     const double *pold = st.pcur ? a.p1 : a.p0;
     const double alpha = st.alpha;  // pending update (normal mode or refresh fold)
     if (D.stop) {
-        if (D.zero_x || D.fold)
+        if (D.ns.done && (D.zero_x || D.fold || a.proj))
             for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
-                a.x[i] = D.zero_x ? 0.0 : folded64(a, i, alpha, pold);
+                a.x[i] = D.zero_x ? 0.0
+                       : (a.proj && i == a.pin) ? a.b[a.pin]
+                       : (D.fold ? folded64(a, i, alpha, pold) : a.x[i]) + D.shift;
         if (lead()) *out = D.ns;
         return;
     }
@@ -377,26 +423,16 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     const bool normal = st.mode == MODE_NORMAL;
     const bool fold = normal || D.fold;
     const double beta = D.beta;
-    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
     double pq = 0.0;
     auto wg = [&](int32_t j) -> double { return normal ? fma(beta, pold[j], a.r[j]) : a.r[j]; };
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-        const int64_t r0 = tile * kTileRows;
-        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
-        int rs, re;
-        load_slab<double>(a.rp, a.col, a.v64, r0, nr, s_col, s_val, rs, re);
-        if ((int)threadIdx.x < nr) {
-            const int64_t i = r0 + threadIdx.x;
-            const double acc = row_product<double>(s_col, s_val, rs, re, wg);
-            const double wi = wg((int32_t)i);
-            if (fold && alpha != 0.0) a.x[i] = folded64(a, i, alpha, pold);
-            pnew[i] = wi;
-            a.q[i] = acc;
-            pq = fma(wi, acc, pq);
-        }
-        __syncthreads();
-    }
+    csr_sweep<double>(a.rp, a.col, a.v64, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, wg), wg);
+        const double wi = wg((int32_t)i);
+        if (fold && alpha != 0.0) a.x[i] = folded64(a, i, alpha, pold);
+        pnew[i] = wi;
+        a.q[i] = acc;
+        pq = fma(wi, acc, pq);
+    });
     pq = block_sum(pq, red);
     if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
     if (lead()) {
@@ -424,9 +460,11 @@ __global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
     const float *pold = st.pcur ? a.p32b : a.p32a;
     const double alpha = st.alpha, s_old = st.scale;
     if (D.stop) {
-        if (D.zero_x || D.fold)
+        if (D.ns.done && (D.zero_x || D.fold || a.proj))
             for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
-                a.x[i] = D.zero_x ? 0.0 : folded32(a, i, alpha, s_old, pold);
+                a.x[i] = D.zero_x ? 0.0
+                       : (a.proj && i == a.pin) ? a.b[a.pin]
+                       : (D.fold ? folded32(a, i, alpha, s_old, pold) : a.x[i]) + D.shift;
                 a.d32[i] = 0.0f;
             }
         if (lead()) *out = D.ns;
@@ -438,33 +476,23 @@ __global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
     const float cf = normal ? (float)D.beta : (float)D.cref;
     const float af = (float)alpha;
     const double inv_s = D.inv_s;
-    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
     double pq = 0.0;
     auto rg = [&](int64_t j) -> float { return normal ? a.r32[j] : (float)(a.r[j] * inv_s); };
     auto wg = [&](int32_t j) -> float { return use_p ? fmaf(cf, pold[j], rg(j)) : rg(j); };
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-        const int64_t r0 = tile * kTileRows;
-        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
-        int rs, re;
-        load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val, rs, re);
-        if ((int)threadIdx.x < nr) {
-            const int64_t i = r0 + threadIdx.x;
-            const float acc = row_product<float>(s_col, s_val, rs, re, wg);
-            const float wi = wg((int32_t)i);
-            if (normal) {
-                if (af != 0.0f) a.d32[i] = fmaf(af, pold[i], a.d32[i]);
-            } else {
-                if (D.fold) a.x[i] = folded32(a, i, alpha, s_old, pold);
-                a.d32[i] = 0.0f;
-                a.r32[i] = rg(i);
-            }
-            pnew[i] = wi;
-            a.q32[i] = acc;
-            pq = fma((double)wi, (double)acc, pq);
+    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        const float acc = neu_fix(a, i, row_product<float>(s_col, s_val, rs, re, wg), wg);
+        const float wi = wg((int32_t)i);
+        if (normal) {
+            if (af != 0.0f) a.d32[i] = fmaf(af, pold[i], a.d32[i]);
+        } else {
+            if (D.fold) a.x[i] = folded32(a, i, alpha, s_old, pold);
+            a.d32[i] = 0.0f;
+            a.r32[i] = rg(i);
         }
-        __syncthreads();
-    }
+        pnew[i] = wi;
+        a.q32[i] = acc;
+        pq = fma((double)wi, (double)acc, pq);
+    });
     pq = block_sum(pq, red);
     if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
     if (lead()) {
@@ -553,15 +581,15 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
     }
 }
 
-// F kernel: when a refresh is pending, r = b - A x' in float64 with the
+// F kernel: when a refresh is pending, r = c - A x' in float64 with the
 // folded iterate x' = x + alpha p (float64) or x + s (d + alpha p) (mixed)
 // gathered on the fly.  x itself is only written by the next A kernel (which
 // never gathers x), so no workgroup can see a half-updated x here.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
-    __shared__ __align__(16) int32_t s_col[kSlab];
-    __shared__ __align__(16) double s_val64[MIXED ? 2 : kSlab];
-    __shared__ __align__(16) float s_val32[MIXED ? kSlab : 4];
+    typedef typename std::conditional<MIXED, float, double>::type VT;
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) VT s_val[kSlabLds];
     __shared__ double red[kBlock / 64];
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
@@ -576,69 +604,62 @@ __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
         if constexpr (MIXED) return folded32(a, j, alpha, s, p32);
         else return folded64(a, j, alpha, p64);
     };
-    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
-    double rr = 0.0;
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-        const int64_t r0 = tile * kTileRows;
-        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
-        int rs, re;
-        double acc = 0.0;
-        if constexpr (MIXED) {
-            load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val32, rs, re);
-            if ((int)threadIdx.x < nr) acc = row_product<double>(s_col, s_val32, rs, re, xg);
-        } else {
-            load_slab<double>(a.rp, a.col, a.v64, r0, nr, s_col, s_val64, rs, re);
-            if ((int)threadIdx.x < nr) acc = row_product<double>(s_col, s_val64, rs, re, xg);
-        }
-        if ((int)threadIdx.x < nr) {
-            const int64_t i = r0 + threadIdx.x;
-            const double ri = a.b[i] - acc;
-            a.r[i] = ri;
-            rr = fma(ri, ri, rr);
-        }
-        __syncthreads();
-    }
+    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
+    double rr = 0.0, rp = 0.0;
+    csr_sweep<VT>(a.rp, a.col, val, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, xg), xg);
+        const double ri = a.c[i] - acc;
+        a.r[i] = ri;
+        rr = fma(ri, ri, rr);
+        if (!(a.proj && i == a.pin)) rp = fma(ri, ri, rp);
+    });
     rr = block_sum(rr, red);
-    if (threadIdx.x == 0) a.partF[blockIdx.x] = rr;
+    rp = block_sum(rp, red);
+    if (threadIdx.x == 0) {
+        a.partF[blockIdx.x] = rr;
+        a.partFp[blockIdx.x] = rp;
+    }
     if (lead()) {
         CgState ns = st;
         ns.pending = 0;
         ns.mode = MODE_REFRESH;
         ns.updates = st.updates + 1;
+        ns.xpin = xg((int32_t)a.pin);  // nobody writes x, p or d in this kernel
         *out = ns;
     }
 }
 
-// Warm start: partial sums of y^T A y and b^T y for gamma, with y[pin] = 0.
+// Warm start: partial sums of y^T A y and c^T y for gamma, with y[pin] = 0
+// (then y^T A_neu y = y^T A_pin y, and c^T y = b^T y - b_pin * sum of y over
+// the pin's neighbours in the projected formulation).
 __global__ void __launch_bounds__(kBlock) warm_gamma(SolveArgs a) {
-    __shared__ __align__(16) int32_t s_col[kSlab];
-    __shared__ __align__(16) float s_val[kSlab];
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
     __shared__ double red[kBlock / 64];
     auto yg = [&](int32_t j) -> double { return j == a.pin ? 0.0 : a.y[j]; };
-    const int64_t ntiles = (a.n + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
     double yay = 0.0, by = 0.0;
-    for (int64_t tile = tr.first; tile < tr.end; tile += tr.step) {
-        const int64_t r0 = tile * kTileRows;
-        const int nr = (int)std::min<int64_t>(kTileRows, a.n - r0);
-        int rs, re;
-        load_slab<float>(a.rp, a.col, a.v32, r0, nr, s_col, s_val, rs, re);
-        if ((int)threadIdx.x < nr) {
-            const int64_t i = r0 + threadIdx.x;
-            const double ay = row_product<double>(s_col, s_val, rs, re, yg);
-            const double yi = yg((int32_t)i);
-            yay = fma(yi, ay, yay);
-            by = fma(a.b[i], yi, by);
-        }
-        __syncthreads();
-    }
+    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        const double ay = row_product<double>(s_col, s_val, rs, re, yg);
+        const double yi = yg((int32_t)i);
+        yay = fma(yi, ay, yay);
+        const double ci = (a.proj && is_pin_nb(a, i)) ? a.b[i] - a.b[a.pin] : a.b[i];
+        by = fma(ci, yi, by);
+    });
     yay = block_sum(yay, red);
     by = block_sum(by, red);
     if (threadIdx.x == 0) {
         a.partG1[blockIdx.x] = yay;
         a.partG2[blockIdx.x] = by;
     }
+}
+
+// Partial sums of b (projected formulation: sum of b for c_pin).
+__global__ void __launch_bounds__(kBlock) rhs_sum(SolveArgs a) {
+    __shared__ double red[kBlock / 64];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) s += a.b[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) a.partS[blockIdx.x] = s;
 }
 
 int net_predict(cfd_net_t net, const cfd_grid *grid, const double *b, double *y, hipStream_t s);
@@ -657,7 +678,10 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     const int max_iters = opts.max_iters > 0 ? opts.max_iters : 100000;
     const double delta = opts.ru_delta > 0.0 ? opts.ru_delta : 0.1;
     const int K = opts.chunk > 0 ? opts.chunk : 16;
-    int rc = ensure_workspace(A, !mixed, mixed, opts.net != nullptr);
+    if (opts.formulation != CFD_FORM_PINNED && opts.formulation != CFD_FORM_PROJECTED)
+        return fail(CFD_EINVAL, "cfd_solve: unknown formulation");
+    const bool proj = opts.formulation == CFD_FORM_PROJECTED;
+    int rc = ensure_workspace(A, !mixed, mixed, opts.net != nullptr, proj);
     if (rc != CFD_OK) return rc;
     Workspace *w = A->ws;
 
@@ -670,11 +694,23 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.tol = tol;
     a.ru_delta = delta;
     a.max_iters = max_iters;
-    a.Ga = grid_spmv(A->n);
+    a.Ga = grid_spmv(A->n, mixed ? 4 : 8);
     a.Gb = grid_vec(A->n);
-    a.Gf = grid_spmv(A->n);
+    a.Gf = a.Ga;
     a.pin = A->pin;
+    a.proj = proj ? 1 : 0;
+    a.nxny = (int64_t)A->nx * A->ny;
+    a.nnb = 0;
+    {
+        const int64_t p = A->pin, nx = A->nx, ny = A->ny, nz = A->nz;
+        const int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+        const int64_t cand[6] = {k > 0 ? p - nx * ny : -1, j > 0 ? p - nx : -1, i > 0 ? p - 1 : -1,
+                                 i < nx - 1 ? p + 1 : -1, j < ny - 1 ? p + nx : -1, k < nz - 1 ? p + nx * ny : -1};
+        for (int q = 0; q < 6; ++q)
+            if (cand[q] >= 0) a.nb[a.nnb++] = cand[q];
+    }
     a.b = b;
+    a.c = proj ? w->c : const_cast<double *>(b);
     a.x = x;
     a.x0 = x0;
     a.y = nullptr;
@@ -694,6 +730,8 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.partF2 = w->part + 3 * gm;
     a.partG1 = w->part + 4 * gm;
     a.partG2 = w->part + 5 * gm;
+    a.partFp = w->part + 7 * gm;
+    a.partS = w->part + 8 * gm;
     a.S = w->S;
 
     CFD_HIP(hipEventRecord(w->ev0, s));
@@ -704,6 +742,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
         a.y = w->y;
         hipLaunchKernelGGL(warm_gamma, dim3(a.Gf), dim3(kBlock), 0, s, a);
     }
+    if (proj) hipLaunchKernelGGL(rhs_sum, dim3(a.Gb), dim3(kBlock), 0, s, a);
     int64_t t = 0;
     if (mixed) hipLaunchKernelGGL(cg_init<true>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
     else hipLaunchKernelGGL(cg_init<false>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+#include <type_traits>
 
 #include "cfdmi.h"
 
@@ -27,7 +28,7 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kTileRows = 256;   // CSR rows per SpMV tile: one row per thread
 constexpr int kMaxRowNnz = 7;    // the 7-point stencil
 constexpr int kXcd = 8;          // MI355X: 8 accelerator complex dies, each with its own L2
-constexpr int kSlab = kTileRows * kMaxRowNnz + 8;  // LDS entries per slab (+ alignment slack)
+constexpr int kSlab = kTileRows * kMaxRowNnz + 4;  // entries a slab may span (+ alignment slack)
 constexpr int kPad = 8;          // extra CSR entries allocated past nnz (vector over-read)
 
 struct Device {
@@ -38,7 +39,7 @@ int device_info(Device *d);
 
 // Grid sizes for the solver's kernels on this device (fixed per device so
 // reductions, which depend on the number of partial sums, are reproducible).
-int grid_spmv(int64_t n);
+int grid_spmv(int64_t n, int value_bytes);
 int grid_vec(int64_t n);
 
 // ---------------------------------------------------------------- matrix handle
@@ -126,37 +127,83 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// Stage the CSR slab of rows [r0, r0+nr) in LDS with 16-byte loads.  On
-// return (after a barrier) s_col/s_val hold entries [ea, e1) where ea =
-// row_ptr[r0] rounded down to a multiple of 4; rs/re are this thread's row
-// bounds relative to ea (empty when threadIdx.x >= nr).
+// Software-pipelined CSR slab loader.  A tile is kTileRows consecutive rows;
+// its slab is the contiguous range [ea, e1) of the column and value arrays
+// (ea = row_ptr[r0] rounded down to a multiple of 4, so every load is a
+// 16-byte vector load).  fetch() issues the loads of a tile into registers;
+// commit() stores them to LDS.  The sweep below fetches tile t+1 while the
+// rows of tile t gather their vector entries, which keeps HBM requests in
+// flight across the whole tile loop.
 template <class VT>
-__device__ inline void load_slab(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                 const VT *__restrict__ val, int64_t r0, int nr,
-                                 int32_t *s_col, VT *s_val, int &rs, int &re) {
-    const int tid = threadIdx.x;
-    const int32_t e0 = rp[r0], e1 = rp[r0 + nr];
-    const int32_t ea = e0 & ~3;
-    const int cnt = e1 - ea;
-    const i32x4 *c4 = reinterpret_cast<const i32x4 *>(col + ea);
-    for (int v = tid; v * 4 < cnt; v += kBlock)
-        reinterpret_cast<i32x4 *>(s_col)[v] = __builtin_nontemporal_load(c4 + v);
-    if constexpr (sizeof(VT) == 8) {
-        const f64x2 *v2 = reinterpret_cast<const f64x2 *>(val + ea);
-        for (int v = tid; v * 2 < cnt; v += kBlock)
-            reinterpret_cast<f64x2 *>(s_val)[v] = __builtin_nontemporal_load(v2 + v);
-    } else {
-        const f32x4 *v4 = reinterpret_cast<const f32x4 *>(val + ea);
-        for (int v = tid; v * 4 < cnt; v += kBlock)
-            reinterpret_cast<f32x4 *>(s_val)[v] = __builtin_nontemporal_load(v4 + v);
+struct SlabPipe {
+    typedef typename std::conditional<sizeof(VT) == 8, f64x2, f32x4>::type VV;
+    static constexpr int kPerV = sizeof(VV) / sizeof(VT);  // values per vector load
+    static constexpr int kVecC = (kSlab + 4 * kBlock - 1) / (4 * kBlock);
+    static constexpr int kVecV = (kSlab + kPerV * kBlock - 1) / (kPerV * kBlock);
+    i32x4 rc[kVecC];
+    VV rv[kVecV];
+    int64_t r0 = 0;
+    int nr = 0, ea = 0, cnt = 0, rs = 0, re = 0;
+
+    __device__ inline void fetch(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                 const VT *__restrict__ val, int64_t n, int64_t tile) {
+        const int tid = threadIdx.x;
+        r0 = tile * kTileRows;
+        nr = (int)(n - r0 < kTileRows ? n - r0 : kTileRows);
+        const int32_t e0 = rp[r0], e1 = rp[r0 + nr];
+        ea = e0 & ~3;
+        cnt = e1 - ea;
+        const i32x4 *c4 = reinterpret_cast<const i32x4 *>(col + ea);
+        const VV *v4 = reinterpret_cast<const VV *>(val + ea);
+#pragma unroll
+        for (int v = 0; v < kVecC; ++v)
+            if ((tid + v * kBlock) * 4 < cnt) rc[v] = __builtin_nontemporal_load(c4 + tid + v * kBlock);
+#pragma unroll
+        for (int v = 0; v < kVecV; ++v)
+            if ((tid + v * kBlock) * kPerV < cnt) rv[v] = __builtin_nontemporal_load(v4 + tid + v * kBlock);
+        if (tid < nr) {
+            rs = rp[r0 + tid] - ea;
+            re = rp[r0 + tid + 1] - ea;
+        } else {
+            rs = re = 0;
+        }
     }
-    if (tid < nr) {
-        rs = rp[r0 + tid] - ea;
-        re = rp[r0 + tid + 1] - ea;
-    } else {
-        rs = re = 0;
+
+    __device__ inline void commit(int32_t *s_col, VT *s_val) const {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int v = 0; v < kVecC; ++v)
+            if ((tid + v * kBlock) * 4 < cnt) reinterpret_cast<i32x4 *>(s_col)[tid + v * kBlock] = rc[v];
+#pragma unroll
+        for (int v = 0; v < kVecV; ++v)
+            if ((tid + v * kBlock) * kPerV < cnt) reinterpret_cast<VV *>(s_val)[tid + v * kBlock] = rv[v];
     }
-    __syncthreads();
+};
+
+// LDS entries reserved per slab: commit() stores whole vectors only below cnt
+// (at most kSlab + 3 entries).
+constexpr int kSlabLds = kSlab + 4;
+
+// Sweep the tiles assigned to this workgroup (XCD-aware schedule).  For each
+// tile, once its slab is in LDS, body(i, rs, re) runs for every row i of the
+// tile owned by this thread (one row per thread), with [rs, re) the row's
+// entries in s_col/s_val.  The call is workgroup-uniform.
+template <class VT, class Body>
+__device__ inline void csr_sweep(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                 const VT *__restrict__ val, int64_t n, int32_t *s_col, VT *s_val, Body &&body) {
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    SlabPipe<VT> P;
+    if (tr.first < tr.end) P.fetch(rp, col, val, n, tr.first);
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t r0 = P.r0;
+        const int nr = P.nr, rs = P.rs, re = P.re;
+        P.commit(s_col, s_val);
+        __syncthreads();
+        if (t + tr.step < tr.end) P.fetch(rp, col, val, n, t + tr.step);
+        if ((int)threadIdx.x < nr) body(r0 + threadIdx.x, rs, re);
+        __syncthreads();
+    }
 }
 
 // Row product over the staged slab: sum_e val[e] * g(col[e]) in ascending

@@ -47,11 +47,14 @@ static int round_grid(int64_t want, int64_t cap) {
     return (int)std::max<int64_t>(g, 1);
 }
 
-// Workgroups for the SpMV-shaped kernels: enough resident waves per CU to
-// keep HBM busy (each workgroup holds ~22 KB of LDS), at most one per tile.
-int grid_spmv(int64_t n) {
+// Workgroups for the SpMV-shaped kernels: 8 resident workgroups (32 waves)
+// per CU measured best on MI355X at 256^3; at most one per tile.  The grid is
+// the same for every SpMV-shaped kernel of the solver so that their partial
+// sums line up.
+int grid_spmv(int64_t n, int value_bytes) {
     const int64_t tiles = (n + kTileRows - 1) / kTileRows;
-    return round_grid(tiles, (int64_t)cus() * 6);
+    // float64 slabs need 21.6 KB of LDS per workgroup: 7 fit in 160 KB
+    return round_grid(tiles, (int64_t)cus() * (value_bytes == 8 ? 7 : 8));
 }
 
 // Workgroups for the streaming vector kernels (4 wave64 each).
@@ -251,21 +254,11 @@ __global__ void __launch_bounds__(kBlock) spmv_kernel(const int32_t *__restrict_
                                                       const int32_t *__restrict__ col,
                                                       const VT *__restrict__ val, int64_t n,
                                                       const VT *__restrict__ x, VT *__restrict__ y) {
-    __shared__ __align__(16) int32_t s_col[kSlab];
-    __shared__ __align__(16) VT s_val[kSlab];
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t r0 = t * kTileRows;
-        const int nr = (int)std::min<int64_t>(kTileRows, n - r0);
-        int rs, re;
-        load_slab<VT>(rp, col, val, r0, nr, s_col, s_val, rs, re);
-        if ((int)threadIdx.x < nr) {
-            const VT acc = row_product<VT>(s_col, s_val, rs, re, [&](int j) { return x[j]; });
-            y[r0 + threadIdx.x] = acc;
-        }
-        __syncthreads();
-    }
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) VT s_val[kSlabLds];
+    csr_sweep<VT>(rp, col, val, n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        y[i] = row_product<VT>(s_col, s_val, rs, re, [&](int j) { return x[j]; });
+    });
 }
 
 // Partial sums of b for the mean.
@@ -295,7 +288,7 @@ extern "C" int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, 
     if (precision != CFD_PREC_FP64 && precision != CFD_PREC_MIXED)
         return fail(CFD_EINVAL, "cfd_spmv: precision must be 0 (float64) or 1 (float32)");
     hipStream_t s = (hipStream_t)stream;
-    const int G = grid_spmv(A->n);
+    const int G = grid_spmv(A->n, precision == CFD_PREC_FP64 ? 8 : 4);
     if (precision == CFD_PREC_FP64)
         hipLaunchKernelGGL(spmv_kernel<double>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val64, A->n,
                            (const double *)x, (double *)y);

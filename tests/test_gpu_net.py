@@ -1,0 +1,215 @@
+"""GPU warm-start network kernels against the FP64 oracle.
+
+Per-layer kernels take bfloat16-representable inputs from the seeded
+generator; the oracle evaluates the same definition in float64.  The GPU
+accumulates in float32 on the matrix cores (bfloat16 products are exact in
+float32), so for a K-term sum |y - y_ref| <= gamma_K * sum|terms| with
+gamma_K = K u / (1 - K u), u = 2^-24 (backward data adds at most 8 folded
+halo terms: K = 27*c_out + 8).
+
+Network-level checks compare against the oracle run on the same bfloat16
+weights; the GPU additionally rounds every activation (and the output
+gradient) to bfloat16 (u_bf16 = 2^-9), so the bars there are relative L2
+errors of 2e-2 (forward: 4 roundings, each amplified by at most ~2 by the
+following layers) and 5e-2 (gradient: 8 roundings on the backward path).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+U32 = 2.0**-24
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2504_03697_amd as m
+    m.load()
+    return m
+
+
+def bits(a):
+    """float32 array of bf16-representable values -> int16 device tensor of bf16 bits."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32) >> 16
+    return torch.from_numpy(u.astype(np.uint16).view(np.int16)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+def gamma(k):
+    return k * U32 / (1 - k * U32)
+
+
+SHAPES = [(1, 16), (16, 16), (16, 1)]
+GRIDS = [(7, 5, 6), (12, 12, 12), (1, 1, 1), (3, 1, 4), (17, 9, 2)]
+
+
+@pytest.mark.parametrize("cin,cout", SHAPES)
+@pytest.mark.parametrize("dims", GRIDS)
+def test_conv_forward(lib, cin, cout, dims):
+    n = int(np.prod(dims))
+    x = synth.bf16_values(n * cin, 1)
+    w = synth.bf16_values(27 * cin * cout, 2, scale=0.3)
+    ref = oracle.conv3d_fwd(dims, x, w, cin, cout)
+    absref = oracle.conv3d_fwd(dims, np.abs(x), np.abs(w), cin, cout)
+    y = host(lib.conv3d_forward(dims, cin, cout, bits(x), bits(w)))
+    assert np.all(np.abs(y - ref) <= gamma(27 * cin) * absref * 1.01 + 1e-30)
+    yr = host(lib.conv3d_forward(dims, cin, cout, bits(x), bits(w), relu=True))
+    assert np.all(np.abs(yr - np.maximum(ref, 0)) <= gamma(27 * cin) * absref * 1.01 + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout", SHAPES)
+@pytest.mark.parametrize("dims", GRIDS)
+def test_conv_backward_data(lib, cin, cout, dims):
+    n = int(np.prod(dims))
+    dy = synth.bf16_values(n * cout, 3)
+    w = synth.bf16_values(27 * cin * cout, 4, scale=0.3)
+    ref = oracle.conv3d_bwd_data(dims, dy, w, cin, cout)
+    absref = oracle.conv3d_bwd_data(dims, np.abs(dy), np.abs(w), cin, cout)
+    dx = host(lib.conv3d_backward_data(dims, cin, cout, bits(dy), bits(w)))
+    assert np.all(np.abs(dx - ref) <= gamma(27 * cout + 8) * absref * 1.01 + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout", SHAPES)
+@pytest.mark.parametrize("dims", GRIDS)
+def test_conv_backward_weight(lib, cin, cout, dims):
+    n = int(np.prod(dims))
+    x = synth.bf16_values(n * cin, 5)
+    dy = synth.bf16_values(n * cout, 6)
+    ref = oracle.conv3d_bwd_weight(dims, x, dy, cin, cout)
+    absref = oracle.conv3d_bwd_weight(dims, np.abs(x), np.abs(dy), cin, cout)
+    dw = host(lib.conv3d_backward_weight(dims, cin, cout, bits(x), bits(dy)))
+    # per-wave float32 partial sums, then a float64 sum of the partials
+    assert np.all(np.abs(dw - ref) <= gamma(n + 64) * absref * 1.01 + 1e-30)
+
+
+def test_conv_bad_channels(lib):
+    with pytest.raises(lib.CfdError):
+        lib.conv3d_forward((4, 4, 4), 1, 1, bits(np.zeros(64, np.float32)), bits(np.zeros(27, np.float32)))
+
+
+def bf16w(theta):
+    return synth.bf16_round_np(theta).astype(np.float64)
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dims", [(12, 10, 9), (16, 16, 16)])
+def test_net_forward(lib, dims):
+    shapes = synth.net_layer_shapes()
+    theta = synth.net_init(1)
+    net = lib.Net(theta)
+    b = synth.smoothed_rhs(dims[0], 3, sigma=2.0) if dims[0] == dims[1] == dims[2] else synth.uniform_rhs(dims, 3)
+    s = np.sqrt(np.mean(b * b))
+    y = host(net.forward(dims, torch.from_numpy(b).cuda()))
+    yref, _ = oracle.net_forward(dims, b / s, bf16w(theta), shapes)
+    assert rel_l2(y, s * yref) <= 2e-2
+    # positively homogeneous: scaling b scales y
+    y2 = host(net.forward(dims, torch.from_numpy(3.0 * b).cuda()))
+    np.testing.assert_allclose(y2, 3.0 * y, rtol=1e-12, atol=1e-300)
+    # b = 0 -> y = 0
+    y0 = host(net.forward(dims, torch.zeros(int(np.prod(dims)), dtype=torch.float64, device="cuda")))
+    assert not y0.any()
+
+
+def test_net_gradient(lib):
+    dims = (10, 9, 8)
+    shapes = synth.net_layer_shapes()
+    theta = synth.net_init(2)
+    net = lib.Net(theta)
+    n = int(np.prod(dims))
+    x = synth.uniform_rhs(dims, 7)
+    tgt = synth.uniform_rhs(dims, 8) * 0.5
+    xb = synth.bf16_round_np(x.astype(np.float32))
+    loss, g = net.gradient(dims, torch.from_numpy(xb).cuda(), torch.from_numpy(tgt.astype(np.float32)).cuda())
+    lref, gref = oracle.net_loss_grad(dims, xb.astype(np.float64), tgt.astype(np.float32).astype(np.float64),
+                                      bf16w(theta), shapes)
+    assert abs(loss - lref) <= 2e-2 * lref
+    off = 0
+    for cin, cout in shapes:
+        k = 27 * cin * cout
+        assert rel_l2(g[off:off + k], gref[off:off + k]) <= 5e-2, (cin, cout)
+        off += k
+    # batch of two identical samples: same mean loss and gradient
+    xx = torch.from_numpy(np.concatenate([xb, xb])).cuda()
+    tt = torch.from_numpy(np.concatenate([tgt, tgt]).astype(np.float32)).cuda()
+    loss2, g2 = net.gradient(dims, xx, tt)
+    np.testing.assert_allclose(loss2, loss, rtol=1e-6)
+    np.testing.assert_allclose(g2, g, rtol=1e-5, atol=1e-9 * np.abs(g).max())
+
+
+def test_adam_step(lib):
+    dims = (8, 8, 8)
+    shapes = synth.net_layer_shapes()
+    theta = synth.net_init(3)
+    net = lib.Net(theta)
+    x = synth.bf16_round_np(synth.uniform_rhs(dims, 1).astype(np.float32))
+    t = synth.uniform_rhs(dims, 2).astype(np.float32)
+    lr = 1e-3
+    net.train_step(dims, torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(), lr)
+    th1 = net.params().astype(np.float64)
+    _, gref = oracle.net_loss_grad(dims, x.astype(np.float64), t.astype(np.float64), bf16w(theta), shapes)
+    ref, _, _ = oracle.adam(theta, np.zeros_like(gref), np.zeros_like(gref), gref, lr, 1)
+    # first step: theta - lr * g / (|g| + eps), i.e. a step of ~lr against the
+    # gradient's sign; entries whose tiny gradient flips sign under bfloat16
+    # rounding differ by at most 2 lr
+    d = np.abs(th1 - ref)
+    assert np.all(d <= 2 * lr * 1.001)
+    assert np.mean(d <= 1e-4 * lr + 1e-7) >= 0.95
+
+
+def test_training_reduces_loss(lib):
+    dims = (12, 12, 12)
+    theta = synth.net_init(4)
+    net = lib.Net(theta)
+    n = int(np.prod(dims))
+    A = oracle.assemble(dims, 0)
+    xs, ts = [], []
+    for s in range(4):
+        b = oracle.rhs_prepare(synth.smoothed_rhs(12, 100 + s, sigma=2.0), 0)
+        p = oracle.cg(A, b, tol=1e-12)[0]
+        r = np.sqrt(np.mean(b * b))
+        xs.append(b / r)
+        ts.append((p - p.mean()) / r)
+    x = torch.from_numpy(np.concatenate(xs).astype(np.float32)).cuda()
+    t = torch.from_numpy(np.concatenate(ts).astype(np.float32)).cuda()
+    l0 = net.train_step(dims, x, t, 3e-3)
+    for _ in range(40):
+        l1 = net.train_step(dims, x, t, 3e-3)
+    assert l1 < 0.8 * l0
+
+
+def test_warm_start_solve(lib):
+    """Solve with the network's prediction as initial guess: same answer as
+    the oracle; a zero network falls back to the zero guess."""
+    n = 16
+    ref = oracle.assemble(n, 0)
+    b = oracle.rhs_prepare(synth.smoothed_rhs(n, 11), 0)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(n, 0)
+    bd = torch.from_numpy(b).cuda()
+    net = lib.Net(synth.net_init(5))
+    for prec in ("fp64", "mixed"):
+        for form in ("pinned", "projected"):
+            x, info = lib.solve(A, bd, net=net, precision=prec, formulation=form)
+            x = x.cpu().numpy()
+            assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+            assert info["used_fallback"] == 0 and np.isfinite(info["gamma"])
+            err = np.linalg.norm((x - x.mean()) - (truth - truth.mean())) / np.linalg.norm(truth - truth.mean())
+            assert err <= 1e-9
+            # the A-optimal scale never makes the start worse than x0 = 0 in
+            # the energy norm, so the initial residual stays bounded
+            assert info["init_residual"] < 10.0
+    zero = lib.Net(np.zeros_like(synth.net_init(5)))
+    x, info = lib.solve(A, bd, net=zero)
+    assert info["used_fallback"] == 1 and info["gamma"] == 0.0 and info["rel_residual"] <= 1e-10

@@ -186,6 +186,50 @@ def test_solve_parity(lib, dims, kind, seed, precision, request):
         assert info["iters"] <= 2.0 * it_ora + 10, (info["iters"], it_ora)
 
 
+@pytest.mark.parametrize("dims,kind,seed", CASES + [((40, 40, 40), "uniform", 9), ((1, 1, 1), "uniform", 0),
+                                             ((2, 3, 1), "uniform", 1)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solve_projected_parity(lib, dims, kind, seed, precision):
+    """Projected formulation (CG on the consistent Neumann system, shifted):
+    the same pinned solution, checked against the oracle's pinned CG."""
+    tol = 1e-10
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, kind, seed)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(dims, 0)
+    x, info = lib.solve(A, dev(b), tol=tol, precision=precision, formulation="projected")
+    x = host(x)
+    assert info["status"] == 0 and info["rel_residual"] <= tol
+    assert x[0] == 0.0  # b[pin] = 0: the shifted solution is exactly 0 there
+    if not np.any(b):
+        assert not np.any(x) and info["iters"] == 0
+        return
+    rr = true_relres(ref, b, x)
+    assert rr <= tol + relres_rounding(ref, b, x)
+    assert abs(rr - info["rel_residual"]) <= 0.05 * tol + relres_rounding(ref, b, x)
+    assert mean_removed_err(x, truth) <= 1e-9 if ref.n > 1 else True
+    np.testing.assert_allclose(x, truth, rtol=0, atol=1e-8 * max(np.abs(truth).max(), 1e-300))
+
+
+def test_solve_projected_general_pin_value(lib):
+    """b[pin] != 0 (an unprepared right-hand side): x[pin] = b[pin] exactly and
+    the other rows solve the pinned system; centre pin."""
+    dims = (11, 9, 7)
+    pin = 5 + 11 * (4 + 9 * 3)
+    ref = oracle.assemble(dims, pin)
+    b = synth.uniform_rhs(dims, 4)
+    b = b - b.mean()
+    b[pin] = 0.37
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(dims, pin)
+    for prec in ("fp64", "mixed"):
+        x, info = lib.solve(A, dev(b), tol=1e-11, precision=prec, formulation="projected")
+        x = host(x)
+        assert info["status"] == 0
+        assert x[pin] == 0.37
+        np.testing.assert_allclose(x, truth, rtol=0, atol=1e-8 * np.abs(truth).max())
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_solve_128_smoothed(lib, precision):
     """128^3, smoothed random right-hand side (2.1M unknowns)."""
@@ -193,12 +237,13 @@ def test_solve_128_smoothed(lib, precision):
     ref = oracle.assemble(n, 0)
     b = make_rhs((n, n, n), "smoothed", 0)
     A = lib.assemble(n, 0)
-    x, info = lib.solve(A, dev(b), tol=1e-10, precision=precision)
-    x = host(x)
-    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
-    assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
     truth = _truth_128(ref, b)
-    assert mean_removed_err(x, truth) <= 1e-9
+    for form in ("pinned", "projected"):
+        x, info = lib.solve(A, dev(b), tol=1e-10, precision=precision, formulation=form)
+        x = host(x)
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+        assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
+        assert mean_removed_err(x, truth) <= 1e-9
 
 
 _TRUTH = {}
@@ -219,7 +264,7 @@ def test_solve_256_mixed_full_size(lib):
     b = make_rhs((n, n, n), "smoothed", 1000)
     A = lib.assemble(n, 0)
     bd = dev(b)
-    x, info = lib.solve(A, bd, tol=1e-10, precision="mixed")
+    x, info = lib.solve(A, bd, tol=1e-10, precision="mixed", formulation="projected")
     x = host(x)
     assert info["status"] == 0 and info["rel_residual"] <= 1e-10
     assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
