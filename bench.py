@@ -3,17 +3,21 @@
 
 A step is one pass of the whole hot path over one synthetic right-hand side
 at 256^3 (16.8M unknowns, 117M nonzeros): right-hand-side preparation,
-learned warm start (when a trained network is available), and the mixed
-FP32/FP64 reliable-update CG solve to a relative residual of 1e-10.  The
-value is the mean time-to-tolerance per solve.  The same right-hand sides are
-then solved by plain FP64 CG for the comparison factor, and the CG SpMV
-kernel's launches are timed with HIP events for the roofline figure.
+learned warm start (when trained weights are present), and the mixed
+FP32/FP64 reliable-update CG solve (projected formulation) to a relative
+residual of 1e-10.  The value is the mean time-to-tolerance per solve.  The
+same right-hand sides are then solved by plain FP64 CG on the pinned matrix
+(the plain method), by FP64 CG in the projected formulation, and by the mixed
+solver without the network, for the comparison factors; the CG SpMV kernel's
+launches inside the timed solves are timed with HIP events for the roofline.
 
 Prints ONE JSON line.  --gpus N > 1 is rejected: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -33,10 +37,37 @@ def a_kernel_bytes(n, nnz, mixed):
     """Algorithmic bytes of one launch of the CG SpMV kernel (normal mode).
 
     CSR: row pointers 4(n+1), columns 4 nnz, values 4 or 8 nnz.
-    Vectors per row: read r, p_old, (d | x), write (d | x), p_new, q.
+    Vectors per row: read r, p_old and the float64 x, write x, p_new, q
+    (r, p, q are float32 in the mixed kernel, float64 otherwise).
     """
     w = 4 if mixed else 8
-    return 4 * (n + 1) + nnz * (4 + w) + 6 * w * n
+    return 4 * (n + 1) + nnz * (4 + w) + 4 * w * n + 16 * n
+
+
+def kernel_source_sha():
+    """Hash of the sources the CG kernels are built from."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2504_03697_amd", "csrc")
+    for f in ("cg.hip", "common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, grid):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC summary
+    (profiles/*.md, line 'traffic-json: {...}'), or None when no summary
+    matches the current kernel sources."""
+    sha = kernel_source_sha()
+    for md in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(md) as fh:
+            for line in fh:
+                if not line.startswith("traffic-json: "):
+                    continue
+                d = json.loads(line[len("traffic-json: "):])
+                if d.get("kernel") == kernel and d.get("grid") == grid and d.get("source_sha") == sha:
+                    return d["bytes_per_launch"]
+    return None
 
 
 def spmv_bytes(n, nnz, w):
@@ -84,9 +115,10 @@ def main():
     torch.cuda.synchronize()
     log(f"{len(rhs)} right-hand sides resident in HBM")
 
-    def run(b, precision, use_net):
+    def run(b, precision, use_net, form="projected"):
         m.rhs_prepare(A, b)
-        x, info = m.solve(A, b, tol=args.tol, precision=precision, net=net if use_net else None, timing=True)
+        x, info = m.solve(A, b, tol=args.tol, precision=precision, net=net if use_net else None, timing=True,
+                          formulation=form)
         return x, info
 
     for i in range(args.warmup):
@@ -103,20 +135,26 @@ def main():
     log(f"mixed{'+learned' if net else ''}: {ms_per_step:.1f} ms/solve, iters "
         f"{[i['iters'] for i in infos]}, relres max {max(i['rel_residual'] for i in infos):.2e}")
 
-    fp64 = None
-    if not args.no_fp64:
-        i64 = []
+    def compare(precision, use_net, form):
+        out = []
         t2 = time.perf_counter()
         for i in range(args.warmup, len(rhs)):
-            _, info = run(rhs[i], "fp64", False)
-            i64.append(info)
+            _, info = run(rhs[i], precision, use_net, form)
+            out.append(info)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        fp64 = {"ms_per_solve": (t3 - t2) * 1e3 / args.steps,
-                "iters": [i["iters"] for i in i64],
-                "rel_residual_max": max(i["rel_residual"] for i in i64),
-                "a_kernel_ms": float(np.mean([i["spmv_ms"] for i in i64 if i["spmv_samples"]]))}
-        log(f"fp64: {fp64['ms_per_solve']:.1f} ms/solve iters {fp64['iters']}")
+        d = {"ms_per_solve": round((t3 - t2) * 1e3 / args.steps, 3), "iters": [i["iters"] for i in out],
+             "rel_residual_max": max(i["rel_residual"] for i in out),
+             "a_kernel_ms": round(float(np.mean([i["spmv_ms"] for i in out if i["spmv_samples"]])), 5)}
+        log(f"{precision} {form}{' +net' if use_net else ''}: {d['ms_per_solve']:.1f} ms/solve iters {d['iters']}")
+        return d
+
+    fp64 = fp64p = mixed_nonet = None
+    if not args.no_fp64:
+        fp64 = compare("fp64", False, "pinned")
+        fp64p = compare("fp64", False, "projected")
+        if net is not None:
+            mixed_nonet = compare("mixed", False, "projected")
 
     # dominant kernel: the mixed-precision CG SpMV kernel, sampled live with
     # HIP events on the solve stream inside the timed region
@@ -124,8 +162,9 @@ def main():
     a_ms = sum(ms * k for ms, k in samples) / max(1, sum(k for _, k in samples))
     a_bytes = a_kernel_bytes(A.n, A.nnz, True)
     achieved = a_bytes / (a_ms * 1e-3) / 1e9 if a_ms > 0 else 0.0
+    traffic = measured_traffic("cg_a32", n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "cg_a32", "bytes_per_launch": a_bytes, "avg_launch_ms": round(a_ms, 5)}
 
     # isolated plain SpMV (FP32 values and vectors), 50 back-to-back launches
@@ -141,6 +180,15 @@ def main():
     torch.cuda.synchronize()
     spmv_ms = e0.elapsed_time(e1) / 50
     spmv_gbs = spmv_bytes(A.n, A.nnz, 4) / (spmv_ms * 1e-3) / 1e9
+
+    # plain copy of known size (256 MiB read, 256 MiB written): the reference
+    # that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes
+    ca = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    torch.cuda.synchronize()
+    del ca, cb
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -163,13 +211,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pressure-Poisson CG, {n}^3 pinned Neumann 7-point CSR, Gaussian-smoothed "
                                f"(sigma=3) random rhs seeds {seeds[args.warmup]}..{seeds[-1]}, tol {args.tol:g}, "
-                               f"mixed FP32/FP64 reliable-update CG" + (" + learned warm start" if net else ""),
+                               f"mixed FP32/FP64 reliable-update CG, projected formulation"
+                               + (" + learned warm start" if net else ""),
                    "grid": n, "unknowns": A.n, "nnz": A.nnz, "learned_warm_start": net is not None},
         "iters": [i["iters"] for i in infos],
         "refreshes": [i["updates"] for i in infos],
         "rel_residual_max": max(i["rel_residual"] for i in infos),
-        "fp64": fp64,
-        "speedup_vs_fp64": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
+        "warm_start": {"init_residual_mean": float(np.mean([i["init_residual"] for i in infos])),
+                       "gamma": [round(i["gamma"], 6) for i in infos],
+                       "fallbacks": int(sum(i["used_fallback"] for i in infos))} if net else None,
+        "fp64_plain_pinned": fp64,
+        "fp64_projected": fp64p,
+        "mixed_projected_no_net": mixed_nonet,
+        "speedup_vs_fp64_plain": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
+        "speedup_vs_fp64_projected": round(fp64p["ms_per_solve"] / ms_per_step, 3) if fp64p else None,
         "spmv_fp32_isolated": {"ms": round(spmv_ms, 5), "gbs": round(spmv_gbs, 1),
                                "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,

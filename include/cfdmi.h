@@ -176,6 +176,8 @@ typedef struct cfd_state {
     double t;            /* simulated time, advanced by dt                   */
     int64_t step;        /* step counter, advanced by 1                      */
     cfd_csr_t A;         /* pinned matrix assembled for `grid`               */
+    double *rhs;         /* optional device double[n]: receives the step's
+                            consistent Poisson right-hand side (NULL: none)  */
 } cfd_state;
 
 /*

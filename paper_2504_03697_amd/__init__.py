@@ -145,7 +145,8 @@ def solve(A: Csr, b, x0=None, tol=1e-10, precision="fp64", net=None, max_iters=0
 class State:
     """Cavity state on the MAC grid, device float64 tensors (cfd_state)."""
 
-    def __init__(self, dims, nu=0.0, rho=1.0, lid_u=1.0, g=(0.0, 0.0, 0.0), pin=0, h=None, device="cuda"):
+    def __init__(self, dims, nu=0.0, rho=1.0, lid_u=1.0, g=(0.0, 0.0, 0.0), pin=0, h=None, device="cuda",
+                 keep_rhs=False):
         torch = _torch()
         self.grid = make_grid(dims, h)
         nx, ny, nz = self.grid.nx, self.grid.ny, self.grid.nz
@@ -155,9 +156,10 @@ class State:
         self.w = torch.zeros(nx * ny * (nz + 1), dtype=torch.float64, device=device)
         self.p = torch.ones(nx * ny * nz, dtype=torch.float64, device=device)
         self.A = Csr(self.dims, pin, self.grid.h)
+        self.rhs = torch.zeros(nx * ny * nz, dtype=torch.float64, device=device) if keep_rhs else None
         self.c = CfdState(self.grid, self.u.data_ptr(), self.v.data_ptr(), self.w.data_ptr(), self.p.data_ptr(),
                           float(nu), float(rho), float(lid_u), float(g[0]), float(g[1]), float(g[2]), 0.0, 0,
-                          self.A.handle)
+                          self.A.handle, self.rhs.data_ptr() if keep_rhs else None)
 
     @property
     def t(self):

@@ -39,7 +39,7 @@ class CfdState(ctypes.Structure):
                 ("p", ctypes.c_void_p), ("nu", ctypes.c_double), ("rho", ctypes.c_double),
                 ("lid_u", ctypes.c_double), ("gx", ctypes.c_double), ("gy", ctypes.c_double),
                 ("gz", ctypes.c_double), ("t", ctypes.c_double), ("step", ctypes.c_int64),
-                ("A", ctypes.c_void_p)]
+                ("A", ctypes.c_void_p), ("rhs", ctypes.c_void_p)]
 
 
 _lib = None

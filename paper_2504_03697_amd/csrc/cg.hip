@@ -20,11 +20,12 @@
 // iterate x' gathered on the fly.  The next A kernel writes x' into x and
 // decides: converged, stop with an error, or continue.
 //
-// Mixed precision (reliable updates): the matrix values, r, p, q and the
-// accumulated correction d are float32, normalised by the residual scale s;
-// x, b, the true residual, every dot product and the scalars are float64.
-// When ||r|| falls below ru_delta times its maximum since the last refresh,
-// x' = x + s (d + alpha p) and r64 = b - A x' are formed in float64; the
+// Mixed precision (reliable updates): the matrix values, r, p and q are
+// float32, normalised by the residual scale s; the solution x is accumulated
+// in float64 (x += s alpha p every iteration), and b, the true residual, every
+// dot product and the scalars are float64.  When ||r|| falls below ru_delta
+// times its maximum since the last refresh, x' = x + s alpha p and
+// r64 = b - A x' are formed in float64; the
 // float32 recurrence restarts from r = r64 / ||r64|| keeping the search
 // direction (rescaled into the new units).
 #include "common.h"
@@ -82,7 +83,7 @@ struct SolveArgs {
     const double *x0;       // initial guess (NULL = none)
     const double *y;        // warm-start prediction (NULL = none)
     double *r, *p0, *p1, *q;          // float64 path (r doubles as r64 in mixed)
-    float *r32, *p32a, *p32b, *q32, *d32;
+    float *r32, *p32a, *p32b, *q32;
     double *partA, *partB, *partF, *partF2, *partG1, *partG2, *partFp, *partS;
     CgState *S;
 };
@@ -91,7 +92,7 @@ struct Workspace {
     int64_t n = 0;
     int gmax = 0;
     double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
-    float *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr, *d32 = nullptr;
+    float *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
     double *y = nullptr;
     double *c = nullptr;     // consistent right-hand side (projected formulation)
     double *part = nullptr;  // 9 * gmax doubles
@@ -105,7 +106,7 @@ void workspace_free(Workspace *ws) {
     if (!ws) return;
     double *dd[] = {ws->r, ws->p0, ws->p1, ws->q, ws->y, ws->c, ws->part};
     for (double *p : dd) if (p) (void)hipFree(p);
-    float *ff[] = {ws->r32, ws->p32a, ws->p32b, ws->q32, ws->d32};
+    float *ff[] = {ws->r32, ws->p32a, ws->p32b, ws->q32};
     for (float *p : ff) if (p) (void)hipFree(p);
     if (ws->S) (void)hipFree(ws->S);
     if (ws->host) (void)hipHostFree(ws->host);
@@ -146,7 +147,6 @@ static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm, bool 
         if (e == hipSuccess) e = alloc(&w->p32a, n);
         if (e == hipSuccess) e = alloc(&w->p32b, n);
         if (e == hipSuccess) e = alloc(&w->q32, n);
-        if (e == hipSuccess) e = alloc(&w->d32, n);
     }
     if (warm && e == hipSuccess) e = alloc(&w->y, n);
     if (proj && e == hipSuccess) e = alloc(&w->c, n);
@@ -256,7 +256,6 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
         const double ri = ci - acc;
         a.r[i] = ri;
         if (a.x != a.x0 || a.y) a.x[i] = xg((int32_t)i);
-        if constexpr (MIXED) a.d32[i] = 0.0f;
         rr = fma(ri, ri, rr);
         if (!(a.proj && i == a.pin)) rp = fma(ri, ri, rp);
         bb = fma(bi, bi, bb);
@@ -286,9 +285,8 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
 __device__ inline double folded64(const SolveArgs &a, int64_t j, double alpha, const double *p) {
     return alpha != 0.0 ? fma(alpha, p[j], a.x[j]) : a.x[j];
 }
-__device__ inline double folded32(const SolveArgs &a, int64_t j, double alpha, double s, const float *p) {
-    const double d = alpha != 0.0 ? fma(alpha, (double)p[j], (double)a.d32[j]) : (double)a.d32[j];
-    return fma(s, d, a.x[j]);
+__device__ inline double folded32(const SolveArgs &a, int64_t j, double salpha, const float *p) {
+    return salpha != 0.0 ? fma(salpha, (double)p[j], a.x[j]) : a.x[j];
 }
 
 // Decision taken at the start of every A kernel from the reduced residual
@@ -343,7 +341,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
             const double bb = reduce_partials(a.partF2, a.Gf, red);
             ns.bnorm = sqrt(bb);
         } else {
-            D.fold = true;  // refresh: x += alpha p (or s (d + alpha p))
+            D.fold = true;  // refresh: x += alpha p (mixed: s alpha p)
         }
         const double tr = sqrt(rr), trp = sqrt(rrp);
         const double bn = ns.bnorm;
@@ -445,10 +443,12 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     }
 }
 
-// A kernel, mixed.  Normal: d += alpha p_old; p = r + beta p_old; q = A p
-// (float32).  Init/refresh: (fold x += s (d + alpha p_old), d = 0)
-// r = r64 / s_new; p = r + cref p_old; q = A p.
-__global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
+// A kernel, mixed.  Normal: x += s alpha p_old (float64); p = r + beta p_old;
+// q = A p (float32).  Init/refresh: (fold x += s alpha p_old) r = r64 / s_new;
+// p = r + cref p_old; q = A p.
+// The kernel is latency-bound: 8 resident workgroups per CU (the most a
+// SIMD can hold, 64 VGPRs per lane) measured fastest at 256^3.
+__global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
     CG_SHARED(float);
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
@@ -464,8 +464,7 @@ __global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
             for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
                 a.x[i] = D.zero_x ? 0.0
                        : (a.proj && i == a.pin) ? a.b[a.pin]
-                       : (D.fold ? folded32(a, i, alpha, s_old, pold) : a.x[i]) + D.shift;
-                a.d32[i] = 0.0f;
+                       : (D.fold ? folded32(a, i, s_old * alpha, pold) : a.x[i]) + D.shift;
             }
         if (lead()) *out = D.ns;
         return;
@@ -474,7 +473,7 @@ __global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
     const bool normal = st.mode == MODE_NORMAL;
     const bool use_p = normal || st.mode == MODE_REFRESH;
     const float cf = normal ? (float)D.beta : (float)D.cref;
-    const float af = (float)alpha;
+    const double sa = s_old * alpha;  // pending x update in true units
     const double inv_s = D.inv_s;
     double pq = 0.0;
     auto rg = [&](int64_t j) -> float { return normal ? a.r32[j] : (float)(a.r[j] * inv_s); };
@@ -483,10 +482,9 @@ __global__ void __launch_bounds__(kBlock) cg_a32(SolveArgs a, int64_t t) {
         const float acc = neu_fix(a, i, row_product<float>(s_col, s_val, rs, re, wg), wg);
         const float wi = wg((int32_t)i);
         if (normal) {
-            if (af != 0.0f) a.d32[i] = fmaf(af, pold[i], a.d32[i]);
+            if (sa != 0.0) a.x[i] = fma(sa, (double)pold[i], a.x[i]);
         } else {
-            if (D.fold) a.x[i] = folded32(a, i, alpha, s_old, pold);
-            a.d32[i] = 0.0f;
+            if (D.fold) a.x[i] = folded32(a, i, s_old * alpha, pold);
             a.r32[i] = rg(i);
         }
         pnew[i] = wi;
@@ -582,7 +580,7 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
 }
 
 // F kernel: when a refresh is pending, r = c - A x' in float64 with the
-// folded iterate x' = x + alpha p (float64) or x + s (d + alpha p) (mixed)
+// folded iterate x' = x + alpha p (float64) or x + s alpha p (mixed)
 // gathered on the fly.  x itself is only written by the next A kernel (which
 // never gathers x), so no workgroup can see a half-updated x here.
 template <bool MIXED>
@@ -601,7 +599,7 @@ __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
     const double *p64 = st.pcur ? a.p1 : a.p0;
     const float *p32 = st.pcur ? a.p32b : a.p32a;
     auto xg = [&](int32_t j) -> double {
-        if constexpr (MIXED) return folded32(a, j, alpha, s, p32);
+        if constexpr (MIXED) return folded32(a, j, s * alpha, p32);
         else return folded64(a, j, alpha, p64);
     };
     const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
@@ -666,6 +664,34 @@ int net_predict(cfd_net_t net, const cfd_grid *grid, const double *b, double *y,
 
 // ---------------------------------------------------------------- host driver
 
+// Workgroups per CU that can be resident at once for a kernel, capped at 8.
+// The SpMV-shaped kernels use a static, XCD-contiguous tile schedule, so
+// every workgroup must be resident: a queued one would run its whole tile
+// range after the others finished.
+template <class K>
+static int resident_per_cu(K kernel) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    return std::min(nb, 8);
+}
+
+struct Grids {
+    int a64, f64, a32, f32;
+};
+
+static const Grids &solver_grids() {
+    static Grids g = [] {
+        Grids r;
+        r.a64 = resident_per_cu(cg_a64);
+        r.f64 = std::min(resident_per_cu(cg_init<false>), resident_per_cu(cg_refresh<false>));
+        r.a32 = resident_per_cu(cg_a32);
+        r.f32 = std::min(std::min(resident_per_cu(cg_init<true>), resident_per_cu(cg_refresh<true>)),
+                         resident_per_cu(warm_gamma));
+        return r;
+    }();
+    return g;
+}
+
 static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts *o,
                       double *x, cfd_solve_info *info, hipStream_t s) {
     cfd_solve_opts opts{};
@@ -694,9 +720,10 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.tol = tol;
     a.ru_delta = delta;
     a.max_iters = max_iters;
-    a.Ga = grid_spmv(A->n, mixed ? 4 : 8);
+    const Grids &gr = solver_grids();
+    a.Ga = grid_tiles(A->n, mixed ? gr.a32 : gr.a64);
     a.Gb = grid_vec(A->n);
-    a.Gf = a.Ga;
+    a.Gf = grid_tiles(A->n, mixed ? gr.f32 : std::min(gr.f64, resident_per_cu(warm_gamma)));
     a.pin = A->pin;
     a.proj = proj ? 1 : 0;
     a.nxny = (int64_t)A->nx * A->ny;
@@ -722,7 +749,6 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.p32a = w->p32a;
     a.p32b = w->p32b;
     a.q32 = w->q32;
-    a.d32 = w->d32;
     const int64_t gm = w->gmax;
     a.partA = w->part;
     a.partB = w->part + gm;

@@ -40,6 +40,7 @@ int device_info(Device *d);
 // Grid sizes for the solver's kernels on this device (fixed per device so
 // reductions, which depend on the number of partial sums, are reproducible).
 int grid_spmv(int64_t n, int value_bytes);
+int grid_tiles(int64_t n, int per_cu);  // SpMV-shaped grid with per_cu workgroups per CU
 int grid_vec(int64_t n);
 
 // ---------------------------------------------------------------- matrix handle

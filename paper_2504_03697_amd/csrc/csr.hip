@@ -52,9 +52,13 @@ static int round_grid(int64_t want, int64_t cap) {
 // the same for every SpMV-shaped kernel of the solver so that their partial
 // sums line up.
 int grid_spmv(int64_t n, int value_bytes) {
-    const int64_t tiles = (n + kTileRows - 1) / kTileRows;
     // float64 slabs need 21.6 KB of LDS per workgroup: 7 fit in 160 KB
-    return round_grid(tiles, (int64_t)cus() * (value_bytes == 8 ? 7 : 8));
+    return grid_tiles(n, value_bytes == 8 ? 7 : 8);
+}
+
+int grid_tiles(int64_t n, int per_cu) {
+    const int64_t tiles = (n + kTileRows - 1) / kTileRows;
+    return round_grid(tiles, (int64_t)cus() * per_cu);
 }
 
 // Workgroups for the streaming vector kernels (4 wave64 each).

@@ -274,6 +274,7 @@ static int step_impl(cfd_state *S, double dt, double tol, const cfd_solve_opts *
     CFD_HIP(hipGetLastError());
     int rc = cfd_rhs_prepare(A, w->b, st);
     if (rc != CFD_OK) return rc;
+    if (S->rhs) CFD_HIP(hipMemcpyAsync(S->rhs, w->b, sizeof(double) * w->n, hipMemcpyDeviceToDevice, st));
     cfd_solve_info inf{};
     rc = solve_internal(A, w->b, nullptr, tol, opts, S->p, &inf, st);
     if (info) *info = inf;

@@ -28,6 +28,7 @@ import numpy as np
 __all__ = [
     "uniform_rhs",
     "smoothed_rhs",
+    "smoothed_rhs_torch",
     "gaussian_kernel_1d",
     "net_init",
     "net_layer_shapes",
@@ -71,6 +72,37 @@ def smoothed_rhs(n: int, seed: int, sigma: float = 3.0) -> np.ndarray:
     a = a - a.mean()
     a = a / np.sqrt(np.mean(a * a))
     return np.ascontiguousarray(a.reshape(-1))
+
+
+def smoothed_rhs_torch(n: int, seed: int, sigma: float = 3.0, device="cuda"):
+    """The smoothed_rhs recipe drawn with torch's generator on `device` (float64).
+
+    Same distribution as smoothed_rhs (different numbers for the same seed):
+    for bulk training data, where host generation would dominate.
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    a = torch.randn((n, n, n), generator=g, device=device, dtype=torch.float64)
+    taps = gaussian_kernel_1d(sigma)
+    r = (len(taps) - 1) // 2
+    for axis in (2, 1, 0):
+        x = a.movedim(axis, 0)
+        # mirror about the wall face (edge sample repeated), as scipy 'reflect'
+        idx = np.arange(-r, n + r)
+        idx = np.where(idx < 0, -idx - 1, idx)
+        idx = np.where(idx >= n, 2 * n - 1 - idx, idx)
+        while (idx < 0).any() or (idx >= n).any():  # grids smaller than the radius
+            idx = np.where(idx < 0, -idx - 1, idx)
+            idx = np.where(idx >= n, 2 * n - 1 - idx, idx)
+        xp = x[torch.from_numpy(idx).to(x.device)]
+        out = torch.zeros_like(x)
+        for m, w in enumerate(taps):
+            out += float(w) * xp[m:m + n]
+        a = out.movedim(0, axis)
+    a = a - a.mean()
+    a = a / torch.sqrt(torch.mean(a * a))
+    return a.reshape(-1).contiguous()
 
 
 def net_layer_shapes(channels: int = 16, layers: int = 4):
