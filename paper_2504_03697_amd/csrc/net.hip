@@ -13,9 +13,10 @@
 // k enumerates (tap, input channel) pairs, two taps per 32-wide K step (14
 // steps for 16 input channels, 1 step for the single-channel input layer),
 // A = the layer's weights (pre-packed per lane), and B = the input values at
-// the clamped neighbour of each voxel (a 16-byte gather per lane).  The
-// 16x16 accumulator holds four consecutive channels of one voxel per lane,
-// so the output is written as one 8-byte (bf16) or 16-byte (float) store.
+// the clamped neighbour of each voxel (a 16-byte read per lane from the
+// workgroup's input brick staged in LDS).  The 16x16 accumulator holds four
+// consecutive channels of one voxel per lane, so the output is written as one
+// 8-byte (bf16) or 16-byte (float) store.
 //
 // Backward data: replicate padding is X_pad[v'] = X[clamp(v')] on the padded
 // grid [-1, n]^3.  Its adjoint is computed in two steps: the same MFMA kernel
@@ -134,6 +135,101 @@ __global__ void __launch_bounds__(kBlock) conv_mfma(Geo g, const uint16_t *__res
                 else ((float *)out)[o] = acc[0];
             }
         }
+    }
+}
+
+// Forward convolution with the input brick staged in LDS.  A workgroup
+// computes an output brick of kBX x kBY x kBZ voxels (16 MFMA tiles of 16
+// voxels along x); its input halo, (kBX+2) x (kBY+2) x (kBZ+2) voxels with
+// replicate padding applied while loading, is read from HBM once into LDS,
+// and every tap's B operand is then a 16-byte LDS read instead of a global
+// gather.
+constexpr int kBX = 16, kBY = 8, kBZ = 2;
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;
+
+template <int CIN, int COUT, bool OUT_BF16>
+__global__ void __launch_bounds__(kBlock) conv_fwd_lds(Geo g, const uint16_t *__restrict__ in,
+                                                       const u16x8 *__restrict__ frag, void *__restrict__ out,
+                                                       int relu) {
+    constexpr int STEPS = CIN == 16 ? 14 : 1;
+    __shared__ __align__(16) uint16_t s_in[kHalo * CIN];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nl = lane & 15, grp = lane >> 4;
+    bf16x8 A[STEPS];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s) A[s] = __builtin_bit_cast(bf16x8, frag[s * 64 + lane]);
+    const int nbx = (g.nx + kBX - 1) / kBX, nby = (g.ny + kBY - 1) / kBY, nbz = (g.nz + kBZ - 1) / kBZ;
+    const int64_t nbricks = (int64_t)nbx * nby * nbz;
+    for (int64_t br = blockIdx.x; br < nbricks; br += gridDim.x) {
+        const int bx0 = (int)(br % nbx) * kBX, by0 = (int)((br / nbx) % nby) * kBY,
+                  bz0 = (int)(br / ((int64_t)nbx * nby)) * kBZ;
+        // stage the halo (clamped coordinates = replicate padding)
+        if constexpr (CIN == 16) {
+            for (int c = threadIdx.x; c < kHalo * 2; c += kBlock) {
+                const int h = c >> 1, half = c & 1;
+                const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+                const int64_t src = (int64_t)clampi(bx0 + hx - 1, 0, g.nx - 1) +
+                                    (int64_t)g.nx * ((int64_t)clampi(by0 + hy - 1, 0, g.ny - 1) +
+                                                     (int64_t)g.ny * clampi(bz0 + hz - 1, 0, g.nz - 1));
+                reinterpret_cast<u16x8 *>(s_in)[c] = *reinterpret_cast<const u16x8 *>(in + src * 16 + 8 * half);
+            }
+        } else {
+            for (int h = threadIdx.x; h < kHalo; h += kBlock) {
+                const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
+                const int64_t src = (int64_t)clampi(bx0 + hx - 1, 0, g.nx - 1) +
+                                    (int64_t)g.nx * ((int64_t)clampi(by0 + hy - 1, 0, g.ny - 1) +
+                                                     (int64_t)g.ny * clampi(bz0 + hz - 1, 0, g.nz - 1));
+                s_in[h] = in[src];
+            }
+        }
+        __syncthreads();
+        // 16 tiles (one x-row of 16 voxels each), 4 per wave
+        for (int ti = wave; ti < kBY * kBZ; ti += kBlock / 64) {
+            const int ty = ti % kBY, tz = ti / kBY;
+            const int x = bx0 + nl, y = by0 + ty, z = bz0 + tz;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) {
+                u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+                if constexpr (CIN == 16) {
+                    const int t = 2 * s + (grp >> 1);
+                    if (t < 27) {
+                        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                        const int h = (nl + 1 + dx) + kHX * ((ty + 1 + dy) + kHY * (tz + 1 + dz));
+                        b = reinterpret_cast<const u16x8 *>(s_in)[2 * h + (grp & 1)];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int t = 8 * grp + e;
+                        if (t < 27) {
+                            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                            b[e] = s_in[(nl + 1 + dx) + kHX * ((ty + 1 + dy) + kHY * (tz + 1 + dz))];
+                        }
+                    }
+                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s], __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+            }
+            if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+            const int64_t o = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+            if (relu) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = acc[q] > 0.f ? acc[q] : 0.f;
+            }
+            if constexpr (COUT == 16) {
+                if constexpr (OUT_BF16) {
+                    u16x4 v = {f2bf(acc[0]), f2bf(acc[1]), f2bf(acc[2]), f2bf(acc[3])};
+                    *reinterpret_cast<u16x4 *>((uint16_t *)out + o * 16 + 4 * grp) = v;
+                } else {
+                    *reinterpret_cast<f32x4 *>((float *)out + o * 16 + 4 * grp) = acc;
+                }
+            } else if (grp == 0) {
+                if constexpr (OUT_BF16) ((uint16_t *)out)[o] = f2bf(acc[0]);
+                else ((float *)out)[o] = acc[0];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -349,6 +445,15 @@ static int grid_waves(int64_t work_items_per_wave_units) {
 
 template <int CIN, int COUT, int MODE, bool OUT_BF16>
 static void launch_conv(const Geo &g, const uint16_t *in, const uint16_t *frag, void *out, int relu, hipStream_t s) {
+    if constexpr (MODE == FWD) {
+        const int64_t nb = (int64_t)((g.nx + kBX - 1) / kBX) * ((g.ny + kBY - 1) / kBY) * ((g.nz + kBZ - 1) / kBZ);
+        Device d;
+        if (device_info(&d) != CFD_OK) d.cus = 256;
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(nb, (int64_t)d.cus * 6));
+        hipLaunchKernelGGL((conv_fwd_lds<CIN, COUT, OUT_BF16>), dim3(blocks), dim3(kBlock), 0, s, g, in,
+                           (const u16x8 *)frag, out, relu);
+        return;
+    }
     const int64_t nout = (int64_t)(g.nx + (MODE == FULL ? 2 : 0)) * (g.ny + (MODE == FULL ? 2 : 0)) *
                          (g.nz + (MODE == FULL ? 2 : 0));
     const int blocks = grid_waves((nout + 15) / 16);

@@ -153,9 +153,11 @@ def make_rhs(dims, kind, seed):
 
 
 MIXED_WHITE_NOISE = pytest.mark.xfail(
-    reason="pinned formulation, mixed precision, white-noise right-hand side: the pinned cell's isolated "
-           "eigenvalue (~1.45/N^3) leaves error along its mode that a 1e-10 residual does not control "
-           "(2.6e-9 measured); the projected Neumann formulation removes that eigenvalue", strict=False)
+    reason="pinned formulation, mixed precision, white-noise right-hand side: a 1e-10 residual leaves "
+           "error in the lowest modes (the pinned cell's isolated eigenvalue ~1.45/N^3 and the smooth modes, "
+           "where the float32 SpMV cancels); 2.6e-9..5e-9 measured on this grid against the 1e-9 bar. The "
+           "projected formulation meets the bar here (7.8e-10); smoothed and cavity right-hand sides meet it "
+           "with a wide margin", strict=False)
 
 
 @pytest.mark.parametrize("dims,kind,seed", CASES)
