@@ -160,3 +160,22 @@ def test_config_128_cavity_50_steps(lib):
     assert np.abs(D).max() <= 1e-8 * np.abs(u).max()
     scale = max(np.abs(u).max(), np.abs(host(S.v)).max(), np.abs(host(S.w)).max())
     assert np.abs(host(M.u) - u).max() <= 1e-6 * scale
+
+
+def test_step_rhs_output(lib):
+    """cfd_state.rhs receives the step's consistent Poisson right-hand side:
+    b = -(rho h / dt) * div(u*) (mean removed, b[pin] = 0), u* the advected
+    and diffused velocity; checked against the oracle's primitives."""
+    n, nu, dt, rho = 12, 0.01, 0.005, 1.0
+    h = 1.0 / n
+    S = lib.State(n, nu=nu, lid_u=1.0, keep_rhs=True)
+    R = oracle.State(n, nu=nu, lid=1.0)
+    for _ in range(3):
+        u0, v0, w0 = R.u.copy(), R.v.copy(), R.w.copy()
+        lib.step(S, dt)
+        oracle.step(R, dt)
+    ua, va, wa = oracle.advect(n, h, 1.0, dt, u0, v0, w0)
+    ud, vd, wd = oracle.diffuse(n, h, 1.0, dt, nu, ua, va, wa)
+    b = oracle.rhs_prepare(-(rho * h / dt) * oracle.divergence(n, ud, vd, wd), 0)
+    got = host(S.rhs)
+    assert np.abs(got - b).max() <= 1e-8 * np.abs(b).max()

@@ -141,3 +141,41 @@ def test_lid_ghost_sets_tangential_shear():
     got = un.reshape(n, n, n + 1)
     np.testing.assert_allclose(got[:, n - 1, 1:n], dt * nu * 2 * U / h**2, rtol=1e-14)
     assert not got[:, : n - 1, :].any()
+
+
+@pytest.mark.parametrize("comp", [0, 1, 2])
+def test_wall_ghosts_by_diffusion(comp):
+    # A uniform tangential value c on every interior face of one component:
+    # explicit diffusion changes a face only through the ghosts beyond the
+    # walls it touches, each contributing (ghost - c) = (2 U_wall - 2c).
+    n, c, U = 6, 0.7, 0.4
+    h = 1.0 / n
+    dt, nu = 1e-3, 0.02
+    su, sv, sw, _ = shapes(n)
+    f = [np.zeros(su), np.zeros(sv), np.zeros(sw)]
+    dims = [(n, n, n + 1), (n, n + 1, n), (n + 1, n, n)]  # (k, j, i) views
+    a = f[comp].reshape(dims[comp])
+    if comp == 0:
+        a[:, :, 1:n] = c
+    elif comp == 1:
+        a[:, 1:n, :] = c
+    else:
+        a[1:n] = c
+    out = oracle.diffuse(n, h, U, dt, nu, *f)[comp].reshape(dims[comp])
+    coef = dt * nu / h**2
+    k_, j_, i_ = np.meshgrid(*(np.arange(d) for d in dims[comp]), indexing="ij")
+    expect = np.full(dims[comp], c)
+    # tangential walls of this component: the two axes other than its own
+    axes = {0: [(j_, n), (k_, n)], 1: [(i_, n), (k_, n)], 2: [(i_, n), (j_, n)]}[comp]
+    for which, (idx, m) in enumerate(axes):
+        lo = idx == 0
+        hi = idx == m - 1
+        lid = comp == 0 and which == 0  # u at the top wall y = 1 (j = n-1 side)
+        expect = expect + coef * np.where(lo, -2 * c, 0.0)
+        expect = expect + coef * np.where(hi, (2 * U if lid else 0.0) - 2 * c, 0.0)
+    # faces next to the component's own (normal) walls see a zero wall face
+    own = {0: i_, 1: j_, 2: k_}[comp]
+    expect = expect + coef * np.where(own == 1, -c, 0.0) + coef * np.where(own == n - 1, -c, 0.0)
+    interior = (own >= 1) & (own <= n - 1)
+    np.testing.assert_allclose(out[interior], expect[interior], rtol=0, atol=1e-15)
+    assert not out[~interior].any()
