@@ -37,11 +37,13 @@ def a_kernel_bytes(n, nnz, mixed):
     """Algorithmic bytes of one launch of the CG SpMV kernel (normal mode).
 
     CSR: row pointers 4(n+1), columns 4 nnz, values 4 or 8 nnz.
-    Vectors per row: read r, p_old and the float64 x, write x, p_new, q
-    (r, p, q are float32 in the mixed kernel, float64 otherwise).
+    Vectors per row: read r and p_old, write p_new and q (float32 in the
+    mixed kernel, float64 otherwise); the float64 kernel also reads and
+    writes x (the mixed path applies its queued x updates in the vector
+    kernel that follows).
     """
     w = 4 if mixed else 8
-    return 4 * (n + 1) + nnz * (4 + w) + 4 * w * n + 16 * n
+    return 4 * (n + 1) + nnz * (4 + w) + 4 * w * n + (0 if mixed else 16 * n)
 
 
 def kernel_source_sha():

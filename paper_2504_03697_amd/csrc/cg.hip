@@ -22,8 +22,13 @@
 //
 // Mixed precision (reliable updates): the matrix values, r, p and q are
 // float32, normalised by the residual scale s; the solution x is accumulated
-// in float64 (x += s alpha p every iteration), and b, the true residual, every
-// dot product and the scalars are float64.  When ||r|| falls below ru_delta
+// in float64 (x += s alpha p for every iteration, in order), and b, the true
+// residual, every dot product and the scalars are float64.  The x updates are
+// deferred: the directions stay in a ring of kDefer float32 buffers with their
+// step lengths s alpha queued in the control state, and the B kernel that
+// fills the queue applies all kDefer updates to x in one read-modify-write
+// pass, oldest first.  That is the float64 x of updating it every iteration,
+// for a quarter of the x traffic.  When ||r|| falls below ru_delta
 // times its maximum since the last refresh, x' = x + s alpha p and
 // r64 = b - A x' are formed in float64; the
 // float32 recurrence restarts from r = r64 / ||r64|| keeping the search
@@ -38,6 +43,12 @@
 
 namespace cfd {
 
+// Mixed path: x updates queued before one pass applies them.  The A kernel
+// writes its direction into the ring slot after the current one; at that
+// point at most kDefer - 1 queued directions occupy the other slots.
+constexpr int kDefer = 4;
+constexpr int kRing = kDefer;
+
 enum Mode : int32_t { MODE_INIT = 0, MODE_NORMAL = 1, MODE_REFRESH = 2 };
 enum Reason : int32_t { R_NONE = 0, R_CONVERGED = 1, R_REFRESH = 2, R_NOCONV = 3, R_BREAKDOWN = 4, R_NONFINITE = 5 };
 
@@ -51,7 +62,7 @@ struct CgState {
     int32_t updates;   // refreshes performed
     int32_t pcur;      // which p buffer holds the current direction
     int32_t fallback;  // warm start rejected
-    int32_t pad_;
+    int32_t npend;     // mixed: x updates not yet applied (directions in the ring)
     double rho;        // r^T r of the residual that generated the current p
     double rho_new;    // latest recursive r^T r (when a refresh is pending)
     double alpha;      // step length not yet folded into x (0 = none)
@@ -62,6 +73,7 @@ struct CgState {
     double init_relres;
     double gamma;      // warm-start scale
     double xpin;       // folded iterate at the pinned cell (projected formulation)
+    double sa[kDefer]; // mixed: step lengths s alpha of the pending updates, oldest first
 };
 
 struct SolveArgs {
@@ -75,6 +87,7 @@ struct SolveArgs {
     int64_t pin;
     int32_t proj;           // 1: CG on the consistent Neumann system, shifted at exit
     int32_t nnb;            // in-domain neighbours of the pinned cell
+    int32_t x_vec2;         // x is 16-byte aligned (paired float64 access)
     int64_t nb[6];
     int64_t nxny;
     const double *b;        // right-hand side of the pinned system
@@ -83,7 +96,8 @@ struct SolveArgs {
     const double *x0;       // initial guess (NULL = none)
     const double *y;        // warm-start prediction (NULL = none)
     double *r, *p0, *p1, *q;          // float64 path (r doubles as r64 in mixed)
-    float *r32, *p32a, *p32b, *q32;
+    float *r32, *q32;
+    float *p32[kRing];      // mixed: ring of direction buffers
     double *partA, *partB, *partF, *partF2, *partG1, *partG2, *partFp, *partS;
     CgState *S;
 };
@@ -92,7 +106,8 @@ struct Workspace {
     int64_t n = 0;
     int gmax = 0;
     double *r = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
-    float *r32 = nullptr, *p32a = nullptr, *p32b = nullptr, *q32 = nullptr;
+    float *r32 = nullptr, *q32 = nullptr;
+    float *p32[kRing] = {};
     double *y = nullptr;
     double *c = nullptr;     // consistent right-hand side (projected formulation)
     double *part = nullptr;  // 9 * gmax doubles
@@ -106,8 +121,9 @@ void workspace_free(Workspace *ws) {
     if (!ws) return;
     double *dd[] = {ws->r, ws->p0, ws->p1, ws->q, ws->y, ws->c, ws->part};
     for (double *p : dd) if (p) (void)hipFree(p);
-    float *ff[] = {ws->r32, ws->p32a, ws->p32b, ws->q32};
+    float *ff[] = {ws->r32, ws->q32};
     for (float *p : ff) if (p) (void)hipFree(p);
+    for (float *p : ws->p32) if (p) (void)hipFree(p);
     if (ws->S) (void)hipFree(ws->S);
     if (ws->host) (void)hipHostFree(ws->host);
     hipEvent_t ee[] = {ws->ev0, ws->ev1, ws->evc[0], ws->evc[1]};
@@ -144,8 +160,7 @@ static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm, bool 
     }
     if (mixed) {
         if (e == hipSuccess) e = alloc(&w->r32, n);
-        if (e == hipSuccess) e = alloc(&w->p32a, n);
-        if (e == hipSuccess) e = alloc(&w->p32b, n);
+        for (int k = 0; k < kRing && e == hipSuccess; ++k) e = alloc(&w->p32[k], n);
         if (e == hipSuccess) e = alloc(&w->q32, n);
     }
     if (warm && e == hipSuccess) e = alloc(&w->y, n);
@@ -280,13 +295,32 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
 }
 
 // Fold the pending update into x for row i.  The refresh kernel gathers
-// exactly this expression, so the residual it computed is that of the x
+// exactly these expressions, so the residual it computed is that of the x
 // written here.
 __device__ inline double folded64(const SolveArgs &a, int64_t j, double alpha, const double *p) {
     return alpha != 0.0 ? fma(alpha, p[j], a.x[j]) : a.x[j];
 }
-__device__ inline double folded32(const SolveArgs &a, int64_t j, double salpha, const float *p) {
-    return salpha != 0.0 ? fma(salpha, (double)p[j], a.x[j]) : a.x[j];
+
+// Mixed path.  Ring buffer k of the directions (uniform select, so the
+// argument block stays in registers).
+__device__ inline const float *ring(const SolveArgs &a, int k) {
+    const float *p = a.p32[0];
+#pragma unroll
+    for (int q = 1; q < kRing; ++q) p = (k == q) ? a.p32[q] : p;
+    return p;
+}
+// Buffer of pending update e (0 = oldest); the newest is the current direction.
+__device__ inline int pend_slot(const CgState &st, int e) {
+    return (st.pcur - (st.npend - 1 - e) + kRing) % kRing;
+}
+// x + every pending update, oldest first: the float64 x that per-iteration
+// updates would hold.
+__device__ inline double folded32(const SolveArgs &a, const CgState &st, int64_t j) {
+    double xj = a.x[j];
+#pragma unroll
+    for (int e = 0; e < kDefer; ++e)
+        if (e < st.npend && st.sa[e] != 0.0) xj = fma(st.sa[e], (double)ring(a, pend_slot(st, e))[j], xj);
+    return xj;
 }
 
 // Decision taken at the start of every A kernel from the reduced residual
@@ -341,7 +375,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
             const double bb = reduce_partials(a.partF2, a.Gf, red);
             ns.bnorm = sqrt(bb);
         } else {
-            D.fold = true;  // refresh: x += alpha p (mixed: s alpha p)
+            D.fold = true;  // refresh (float64 path): this A kernel folds x += alpha p
         }
         const double tr = sqrt(rr), trp = sqrt(rrp);
         const double bn = ns.bnorm;
@@ -443,9 +477,10 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     }
 }
 
-// A kernel, mixed.  Normal: x += s alpha p_old (float64); p = r + beta p_old;
-// q = A p (float32).  Init/refresh: (fold x += s alpha p_old) r = r64 / s_new;
-// p = r + cref p_old; q = A p.
+// A kernel, mixed.  Normal: p = r + beta p_old; q = A p (float32).
+// Init/refresh: r = r64 / s_new; p = r + cref p_old; q = A p.  x is written
+// only when the solve ends (queued updates, projected shift); the B kernels
+// apply the queue otherwise.
 // The kernel is latency-bound: 8 resident workgroups per CU (the most a
 // SIMD can hold, 64 VGPRs per lane) measured fastest at 256^3.
 __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
@@ -457,23 +492,21 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
         return;
     }
     const Decision D = decide<true>(a, st, red);
-    const float *pold = st.pcur ? a.p32b : a.p32a;
-    const double alpha = st.alpha, s_old = st.scale;
+    const float *pold = ring(a, st.pcur);
     if (D.stop) {
-        if (D.ns.done && (D.zero_x || D.fold || a.proj))
+        if (D.ns.done && (D.zero_x || st.npend > 0 || a.proj))
             for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
                 a.x[i] = D.zero_x ? 0.0
                        : (a.proj && i == a.pin) ? a.b[a.pin]
-                       : (D.fold ? folded32(a, i, s_old * alpha, pold) : a.x[i]) + D.shift;
+                       : folded32(a, st, i) + D.shift;
             }
         if (lead()) *out = D.ns;
         return;
     }
-    float *pnew = st.pcur ? a.p32a : a.p32b;
+    float *pnew = const_cast<float *>(ring(a, (st.pcur + 1) % kRing));
     const bool normal = st.mode == MODE_NORMAL;
     const bool use_p = normal || st.mode == MODE_REFRESH;
     const float cf = normal ? (float)D.beta : (float)D.cref;
-    const double sa = s_old * alpha;  // pending x update in true units
     const double inv_s = D.inv_s;
     double pq = 0.0;
     auto rg = [&](int64_t j) -> float { return normal ? a.r32[j] : (float)(a.r[j] * inv_s); };
@@ -481,12 +514,7 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
     csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
         const float acc = neu_fix(a, i, row_product<float>(s_col, s_val, rs, re, wg), wg);
         const float wi = wg((int32_t)i);
-        if (normal) {
-            if (sa != 0.0) a.x[i] = fma(sa, (double)pold[i], a.x[i]);
-        } else {
-            if (D.fold) a.x[i] = folded32(a, i, s_old * alpha, pold);
-            a.r32[i] = rg(i);
-        }
+        if (!normal) a.r32[i] = rg(i);
         pnew[i] = wi;
         a.q32[i] = acc;
         pq = fma((double)wi, (double)acc, pq);
@@ -497,7 +525,7 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
         CgState ns = D.ns;
         ns.mode = MODE_NORMAL;
         ns.iters = st.iters + 1;
-        ns.pcur = 1 - st.pcur;
+        ns.pcur = (st.pcur + 1) % kRing;
         ns.alpha = 0.0;
         *out = ns;
     }
@@ -526,9 +554,45 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
         return;
     }
     double rr = 0.0;
+    double sa_new = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if constexpr (MIXED) {
+        // Queue x += s alpha p for this iteration's direction (the ring's
+        // current slot).  When that fills the queue, apply all kDefer updates
+        // to x here, oldest first; the older directions sit in the slots
+        // before the current one.
+        sa_new = st.scale * alpha;
+        if (st.npend == kDefer - 1) {
+            const float *pe[kDefer];
+            double se[kDefer];
+#pragma unroll
+            for (int e = 0; e < kDefer; ++e) {
+                pe[e] = ring(a, (st.pcur - (kDefer - 1 - e) + kRing) % kRing);
+                se[e] = e < kDefer - 1 ? st.sa[e] : sa_new;
+            }
+            const int64_t n2 = a.x_vec2 ? a.n / 2 : 0;
+            double2 *x2 = reinterpret_cast<double2 *>(a.x);
+            for (int64_t v = first; v < n2; v += stride) {
+                double2 xv = x2[v];
+#pragma unroll
+                for (int e = 0; e < kDefer; ++e) {
+                    const float2 pv = reinterpret_cast<const float2 *>(pe[e])[v];
+                    if (se[e] != 0.0) {
+                        xv.x = fma(se[e], (double)pv.x, xv.x);
+                        xv.y = fma(se[e], (double)pv.y, xv.y);
+                    }
+                }
+                x2[v] = xv;
+            }
+            for (int64_t i = n2 * 2 + first; i < a.n; i += stride) {
+                double xi = a.x[i];
+#pragma unroll
+                for (int e = 0; e < kDefer; ++e)
+                    if (se[e] != 0.0) xi = fma(se[e], (double)pe[e][i], xi);
+                a.x[i] = xi;
+            }
+        }
         const float af = (float)alpha;
         const int64_t nv = a.n / 4;
         float4 *r4 = reinterpret_cast<float4 *>(a.r32);
@@ -575,13 +639,23 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
     if (lead()) {
         CgState ns = st;
         ns.alpha = alpha;
+        if (MIXED) {
+            if (st.npend < kDefer - 1) {
+#pragma unroll
+                for (int e = 0; e < kDefer - 1; ++e)
+                    if (e == st.npend) ns.sa[e] = sa_new;
+                ns.npend = st.npend + 1;
+            } else {
+                ns.npend = 0;  // applied above
+            }
+        }
         *out = ns;
     }
 }
 
 // F kernel: when a refresh is pending, r = c - A x' in float64 with the
-// folded iterate x' = x + alpha p (float64) or x + s alpha p (mixed)
-// gathered on the fly.  x itself is only written by the next A kernel (which
+// folded iterate x' = x + alpha p (float64) or x plus every pending
+// s alpha p (mixed) gathered on the fly.  x itself is only written by the next A kernel (which
 // never gathers x), so no workgroup can see a half-updated x here.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
@@ -595,11 +669,10 @@ __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
         if (lead()) *out = st;
         return;
     }
-    const double alpha = st.alpha, s = st.scale;
+    const double alpha = st.alpha;
     const double *p64 = st.pcur ? a.p1 : a.p0;
-    const float *p32 = st.pcur ? a.p32b : a.p32a;
     auto xg = [&](int32_t j) -> double {
-        if constexpr (MIXED) return folded32(a, j, s * alpha, p32);
+        if constexpr (MIXED) return folded32(a, st, j);
         else return folded64(a, j, alpha, p64);
     };
     const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
@@ -739,6 +812,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.b = b;
     a.c = proj ? w->c : const_cast<double *>(b);
     a.x = x;
+    a.x_vec2 = ((uintptr_t)x % 16) == 0 ? 1 : 0;
     a.x0 = x0;
     a.y = nullptr;
     a.r = w->r;
@@ -746,8 +820,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.p1 = w->p1;
     a.q = w->q;
     a.r32 = w->r32;
-    a.p32a = w->p32a;
-    a.p32b = w->p32b;
+    for (int k = 0; k < kRing; ++k) a.p32[k] = w->p32[k];
     a.q32 = w->q32;
     const int64_t gm = w->gmax;
     a.partA = w->part;

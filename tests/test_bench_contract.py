@@ -17,7 +17,7 @@ def test_algorithmic_bytes():
     sys.path.insert(0, ROOT)
     import bench
     n, nnz = 256**3, 7 * 256**3 - 6 * 256**2 - 6
-    assert bench.a_kernel_bytes(n, nnz, True) == 4 * (n + 1) + 8 * nnz + 32 * n == 1540358100
+    assert bench.a_kernel_bytes(n, nnz, True) == 4 * (n + 1) + 8 * nnz + 16 * n == 1271922644
     assert bench.a_kernel_bytes(n, nnz, False) == 4 * (n + 1) + 12 * nnz + 48 * n
     assert bench.spmv_bytes(n, nnz, 4) == 4 * (n + 1) + 8 * nnz + 8 * n
     assert len(bench.kernel_source_sha()) == 16
