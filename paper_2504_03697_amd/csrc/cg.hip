@@ -511,10 +511,13 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
     double pq = 0.0;
     auto rg = [&](int64_t j) -> float { return normal ? a.r32[j] : (float)(a.r[j] * inv_s); };
     auto wg = [&](int32_t j) -> float { return use_p ? fmaf(cf, pold[j], rg(j)) : rg(j); };
-    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+    // own row's r and p_old, loaded a tile ahead with the CSR slab (measured
+    // 7.6% faster at 256^3 than loading them in the row body)
+    auto own = [&](int64_t i) -> float2 { return make_float2(rg(i), use_p ? pold[i] : 0.0f); };
+    csr_sweep_pre<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, own, [&](int64_t i, int rs, int re, float2 o) {
         const float acc = neu_fix(a, i, row_product<float>(s_col, s_val, rs, re, wg), wg);
-        const float wi = wg((int32_t)i);
-        if (!normal) a.r32[i] = rg(i);
+        const float wi = use_p ? fmaf(cf, o.y, o.x) : o.x;
+        if (!normal) a.r32[i] = o.x;
         pnew[i] = wi;
         a.q32[i] = acc;
         pq = fma((double)wi, (double)acc, pq);

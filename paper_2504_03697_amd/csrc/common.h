@@ -207,6 +207,37 @@ __device__ inline void csr_sweep(const int32_t *__restrict__ rp, const int32_t *
     }
 }
 
+// csr_sweep with per-row operands fetched one tile ahead as well: pre(i)
+// loads what the body needs from row i's own vector entries, for the next
+// tile while the current one computes; body(i, rs, re, v) gets the value.
+template <class VT, class Pre, class Body>
+__device__ inline void csr_sweep_pre(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                     const VT *__restrict__ val, int64_t n, int32_t *s_col, VT *s_val, Pre &&pre,
+                                     Body &&body) {
+    using T = decltype(pre(int64_t(0)));
+    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    SlabPipe<VT> P;
+    T next{};
+    if (tr.first < tr.end) {
+        P.fetch(rp, col, val, n, tr.first);
+        if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
+    }
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t r0 = P.r0;
+        const int nr = P.nr, rs = P.rs, re = P.re;
+        const T cur = next;
+        P.commit(s_col, s_val);
+        __syncthreads();
+        if (t + tr.step < tr.end) {
+            P.fetch(rp, col, val, n, t + tr.step);
+            if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
+        }
+        if ((int)threadIdx.x < nr) body(r0 + threadIdx.x, rs, re, cur);
+        __syncthreads();
+    }
+}
+
 // Row product over the staged slab: sum_e val[e] * g(col[e]) in ascending
 // column order.  Rows of the 7-point matrix hold at most 7 entries.
 template <class Acc, class VT, class G>
