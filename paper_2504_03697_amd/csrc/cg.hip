@@ -460,9 +460,9 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     csr_sweep<double>(a.rp, a.col, a.v64, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
         const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, wg), wg);
         const double wi = wg((int32_t)i);
-        if (fold && alpha != 0.0) a.x[i] = folded64(a, i, alpha, pold);
-        pnew[i] = wi;
-        a.q[i] = acc;
+        if (fold && alpha != 0.0) store_stream(a.x + i, folded64(a, i, alpha, pold));
+        store_stream(pnew + i, wi);
+        store_stream(a.q + i, acc);
         pq = fma(wi, acc, pq);
     });
     pq = block_sum(pq, red);
@@ -517,9 +517,9 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
     csr_sweep_pre<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, own, [&](int64_t i, int rs, int re, float2 o) {
         const float acc = neu_fix(a, i, row_product<float>(s_col, s_val, rs, re, wg), wg);
         const float wi = use_p ? fmaf(cf, o.y, o.x) : o.x;
-        if (!normal) a.r32[i] = o.x;
-        pnew[i] = wi;
-        a.q32[i] = acc;
+        if (!normal) store_stream(a.r32 + i, o.x);
+        store_stream(pnew + i, wi);
+        store_stream(a.q32 + i, acc);
         pq = fma((double)wi, (double)acc, pq);
     });
     pq = block_sum(pq, red);
@@ -575,18 +575,18 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
                 se[e] = e < kDefer - 1 ? st.sa[e] : sa_new;
             }
             const int64_t n2 = a.x_vec2 ? a.n / 2 : 0;
-            double2 *x2 = reinterpret_cast<double2 *>(a.x);
+            f64x2 *x2 = reinterpret_cast<f64x2 *>(a.x);
             for (int64_t v = first; v < n2; v += stride) {
-                double2 xv = x2[v];
+                f64x2 xv = __builtin_nontemporal_load(x2 + v);
 #pragma unroll
                 for (int e = 0; e < kDefer; ++e) {
-                    const float2 pv = reinterpret_cast<const float2 *>(pe[e])[v];
+                    const f32x2 pv = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(pe[e]) + v);
                     if (se[e] != 0.0) {
                         xv.x = fma(se[e], (double)pv.x, xv.x);
                         xv.y = fma(se[e], (double)pv.y, xv.y);
                     }
                 }
-                x2[v] = xv;
+                store_stream(x2 + v, xv);
             }
             for (int64_t i = n2 * 2 + first; i < a.n; i += stride) {
                 double xi = a.x[i];
@@ -598,16 +598,16 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
         }
         const float af = (float)alpha;
         const int64_t nv = a.n / 4;
-        float4 *r4 = reinterpret_cast<float4 *>(a.r32);
-        const float4 *q4 = reinterpret_cast<const float4 *>(a.q32);
+        f32x4 *r4 = reinterpret_cast<f32x4 *>(a.r32);
+        const f32x4 *q4 = reinterpret_cast<const f32x4 *>(a.q32);
         for (int64_t v = first; v < nv; v += stride) {
-            float4 r = r4[v];
-            const float4 q = q4[v];
+            f32x4 r = __builtin_nontemporal_load(r4 + v);
+            const f32x4 q = __builtin_nontemporal_load(q4 + v);
             r.x = fmaf(-af, q.x, r.x);
             r.y = fmaf(-af, q.y, r.y);
             r.z = fmaf(-af, q.z, r.z);
             r.w = fmaf(-af, q.w, r.w);
-            r4[v] = r;
+            store_stream(r4 + v, r);
             rr = fma((double)r.x, (double)r.x, rr);
             rr = fma((double)r.y, (double)r.y, rr);
             rr = fma((double)r.z, (double)r.z, rr);
@@ -620,14 +620,14 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
         }
     } else {
         const int64_t nv = a.n / 2;
-        double2 *r2 = reinterpret_cast<double2 *>(a.r);
-        const double2 *q2 = reinterpret_cast<const double2 *>(a.q);
+        f64x2 *r2 = reinterpret_cast<f64x2 *>(a.r);
+        const f64x2 *q2 = reinterpret_cast<const f64x2 *>(a.q);
         for (int64_t v = first; v < nv; v += stride) {
-            double2 r = r2[v];
-            const double2 q = q2[v];
+            f64x2 r = __builtin_nontemporal_load(r2 + v);
+            const f64x2 q = __builtin_nontemporal_load(q2 + v);
             r.x = fma(-alpha, q.x, r.x);
             r.y = fma(-alpha, q.y, r.y);
-            r2[v] = r;
+            store_stream(r2 + v, r);
             rr = fma(r.x, r.x, rr);
             rr = fma(r.y, r.y, rr);
         }

@@ -127,6 +127,15 @@ __device__ inline double reduce_partials(const double *part, int count, double *
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Store with the non-temporal hint, for vectors far larger than the L2 that
+// the next kernel re-reads from HBM anyway: their lines then do not displace
+// the gathered neighbour planes the current sweep reuses from L2.
+template <class T>
+__device__ inline void store_stream(T *p, T v) {
+    __builtin_nontemporal_store(v, p);
+}
 
 // Software-pipelined CSR slab loader.  A tile is kTileRows consecutive rows;
 // its slab is the contiguous range [ea, e1) of the column and value arrays

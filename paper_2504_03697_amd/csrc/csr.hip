@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) spmv_kernel(const int32_t *__restrict_
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) VT s_val[kSlabLds];
     csr_sweep<VT>(rp, col, val, n, s_col, s_val, [&](int64_t i, int rs, int re) {
-        y[i] = row_product<VT>(s_col, s_val, rs, re, [&](int j) { return x[j]; });
+        store_stream(y + i, row_product<VT>(s_col, s_val, rs, re, [&](int j) { return x[j]; }));
     });
 }
 
