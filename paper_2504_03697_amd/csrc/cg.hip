@@ -601,8 +601,10 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
         f32x4 *r4 = reinterpret_cast<f32x4 *>(a.r32);
         const f32x4 *q4 = reinterpret_cast<const f32x4 *>(a.q32);
         for (int64_t v = first; v < nv; v += stride) {
-            f32x4 r = __builtin_nontemporal_load(r4 + v);
-            const f32x4 q = __builtin_nontemporal_load(q4 + v);
+            // plain loads (measured faster than non-temporal ones here: the
+            // lines they leave cached serve the next A kernel), streamed store
+            f32x4 r = r4[v];
+            const f32x4 q = q4[v];
             r.x = fmaf(-af, q.x, r.x);
             r.y = fmaf(-af, q.y, r.y);
             r.z = fmaf(-af, q.z, r.z);
@@ -623,8 +625,8 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
         f64x2 *r2 = reinterpret_cast<f64x2 *>(a.r);
         const f64x2 *q2 = reinterpret_cast<const f64x2 *>(a.q);
         for (int64_t v = first; v < nv; v += stride) {
-            f64x2 r = __builtin_nontemporal_load(r2 + v);
-            const f64x2 q = __builtin_nontemporal_load(q2 + v);
+            f64x2 r = r2[v];
+            const f64x2 q = q2[v];
             r.x = fma(-alpha, q.x, r.x);
             r.y = fma(-alpha, q.y, r.y);
             store_stream(r2 + v, r);
