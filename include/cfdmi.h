@@ -108,6 +108,7 @@ typedef struct cfd_net *cfd_net_t;
 
 enum { CFD_PREC_FP64 = 0, CFD_PREC_MIXED = 1 };
 enum { CFD_FORM_PINNED = 0, CFD_FORM_PROJECTED = 1 };
+enum { CFD_GUESS_ZERO = 0, CFD_GUESS_PREVIOUS = 1 };
 
 typedef struct cfd_solve_opts {
     int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout.
@@ -133,7 +134,14 @@ typedef struct cfd_solve_opts {
                             by a constant; x is shifted so x_pin = b_pin.
                             Same answer, without the pinned cell's isolated
                             small eigenvalue.                                */
-    int32_t reserved_;
+    int32_t step_guess;  /* cfd_step only (ignored by cfd_solve):
+                            CFD_GUESS_ZERO: the pressure solve starts from
+                            zero (or from the network when `net` is set).
+                            CFD_GUESS_PREVIOUS: it starts from the pressure
+                            already in state->p, the previous step's (the
+                            paper's pressure is a field carried from step to
+                            step, starting uniform, Sec. 3); CFD_EINVAL
+                            together with `net`.                             */
 } cfd_solve_opts;
 
 typedef struct cfd_solve_info {
@@ -186,7 +194,8 @@ typedef struct cfd_state {
  *  (first-order back-trace, trilinear sampling, departure point clamped to
  *  the domain) -> explicit viscosity (u += dt*nu*Lap_h u) -> pressure
  *  correction: D = sum of face-flux differences, b = -(rho*h/dt)*D made
- *  consistent, A p = b solved from a zero guess to tol with `opts`, then
+ *  consistent, A p = b solved to tol with `opts` (from a zero guess, the
+ *  network's prediction, or the previous pressure: opts->step_guess), then
  *  interior faces u -= (dt/(rho*h))*(p_right - p_left).
  * Walls are no-slip; tangential values outside the domain are ghosts
  * 2*U_wall - inside (U_wall = lid_u for u on the lid, else 0).

@@ -171,8 +171,13 @@ class State:
 
 
 def step(S: State, dt, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0, chunk=0,
-         formulation="pinned"):
+         formulation="pinned", guess="zero"):
+    """One time step (cfd_step).  guess: "zero" (or the network's prediction
+    when net is given) or "previous" (start from the pressure in S.p)."""
     opts = solve_opts(precision, max_iters, ru_delta, net, chunk, False, formulation)
+    if guess not in ("zero", "previous"):
+        raise ValueError("guess must be 'zero' or 'previous'")
+    opts.step_guess = 1 if guess == "previous" else 0
     info = CfdSolveInfo()
     check(load().cfd_step(ctypes.byref(S.c), float(dt), float(tol), ctypes.byref(opts), ctypes.byref(info),
                           _stream()))

@@ -241,6 +241,10 @@ static int step_impl(cfd_state *S, double dt, double tol, const cfd_solve_opts *
     if (!(gr.h > 0.0) || !(S->rho > 0.0)) return fail(CFD_EINVAL, "cfd_step: h and rho must be > 0");
     if (S->nu < 0.0 || dt * S->nu * 6.0 / (gr.h * gr.h) > 1.0)
         return fail(CFD_EINVAL, "cfd_step: explicit viscosity unstable (need dt*nu*6/h^2 <= 1)");
+    const int guess = opts ? opts->step_guess : CFD_GUESS_ZERO;
+    if (guess != CFD_GUESS_ZERO && guess != CFD_GUESS_PREVIOUS) return fail(CFD_EINVAL, "cfd_step: unknown step_guess");
+    if (guess == CFD_GUESS_PREVIOUS && opts->net)
+        return fail(CFD_EINVAL, "cfd_step: give either a warm-start network or the previous-pressure guess");
     StepWs *w = (StepWs *)A->step_ws;
     if (!w) {
         w = new StepWs();
@@ -276,7 +280,9 @@ static int step_impl(cfd_state *S, double dt, double tol, const cfd_solve_opts *
     if (rc != CFD_OK) return rc;
     if (S->rhs) CFD_HIP(hipMemcpyAsync(S->rhs, w->b, sizeof(double) * w->n, hipMemcpyDeviceToDevice, st));
     cfd_solve_info inf{};
-    rc = solve_internal(A, w->b, nullptr, tol, opts, S->p, &inf, st);
+    // previous-pressure guess: x0 and x are the same array (the solver reads
+    // x0 only in its first kernel, before anything writes x)
+    rc = solve_internal(A, w->b, guess == CFD_GUESS_PREVIOUS ? S->p : nullptr, tol, opts, S->p, &inf, st);
     if (info) *info = inf;
     if (rc != CFD_OK) return rc;
     hipLaunchKernelGGL(correct_kernel, dim3(gf), dim3(kBlock), 0, st, g, f, dt / (S->rho * gr.h), (const double *)S->p);

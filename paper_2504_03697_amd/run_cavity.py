@@ -3,14 +3,16 @@
 
 Each step is the library's fractional step (cfd_step): forces, semi-
 Lagrangian advection, explicit viscosity, then the pressure-Poisson solve
-(the hot path) and the gradient correction.  Runs the same steps twice when
---compare is given: once with the solver options under test and once with
-plain FP64 CG on the pinned matrix, from the same initial state, and reports
-iterations, solve times and the velocity difference after each step.
+(the hot path) and the gradient correction.  With --compare the same steps
+also run with plain FP64 CG on the pinned matrix from a zero guess, and with
+--previous with the solver options under test but started from the previous
+step's pressure instead of the network (the non-learned warm start), each
+from the same initial state; the report gives iterations, solve times and
+the velocity difference to the plain FP64 run after each step.
 
 Example (384^3, Re = 1000, mixed + learned + projected vs plain FP64):
     python run_cavity.py --n 384 --re 1000 --dt 0.001 --steps 20 \\
-        --precision mixed --formulation projected --net weights/warmstart.npy --compare
+        --precision mixed --formulation projected --net weights/warmstart.npy --compare --previous
 """
 from __future__ import annotations
 
@@ -39,6 +41,8 @@ def main():
     ap.add_argument("--formulation", default="pinned", choices=["pinned", "projected"])
     ap.add_argument("--net", default=None, help="warm-start weights (.npy)")
     ap.add_argument("--compare", action="store_true", help="also run plain FP64 pinned CG from the same state")
+    ap.add_argument("--previous", action="store_true",
+                    help="also run the same solver started from the previous step's pressure (no network)")
     args = ap.parse_args()
 
     import numpy as np
@@ -54,6 +58,7 @@ def main():
     net = m.Net(np.load(args.net)) if args.net else None
     S = m.State(n, nu=nu, lid_u=1.0)
     R = m.State(n, nu=nu, lid_u=1.0) if args.compare else None
+    P = m.State(n, nu=nu, lid_u=1.0) if args.previous else None
     log(f"{n}^3, Re={args.re:g}, dt={dt:g}, {args.steps} steps, {args.precision}/{args.formulation}"
         f"{' + learned warm start' if net else ''}")
     rows = []
@@ -61,6 +66,10 @@ def main():
         info = m.step(S, dt, tol=args.tol, precision=args.precision, net=net, formulation=args.formulation)
         row = {"step": s + 1, "iters": info["iters"], "seconds": round(info["seconds"], 4),
                "rel_residual": info["rel_residual"], "init_residual": info["init_residual"]}
+        if P is not None:
+            ip = m.step(P, dt, tol=args.tol, precision=args.precision, formulation=args.formulation, guess="previous")
+            row.update({"prev_iters": ip["iters"], "prev_seconds": round(ip["seconds"], 4),
+                        "prev_init_residual": ip["init_residual"]})
         if R is not None:
             ir = m.step(R, dt, tol=args.tol, precision="fp64", formulation="pinned")
             row.update({"fp64_iters": ir["iters"], "fp64_seconds": round(ir["seconds"], 4)})
@@ -74,11 +83,16 @@ def main():
             "solve_seconds": round(sum(r["seconds"] for r in rows), 3),
             "iters_total": int(sum(r["iters"] for r in rows)),
             "max_rel_residual": max(r["rel_residual"] for r in rows)}
+    if P is not None:
+        summ["prev_solve_seconds"] = round(sum(r["prev_seconds"] for r in rows), 3)
+        summ["prev_iters_total"] = int(sum(r["prev_iters"] for r in rows))
     if R is not None:
         summ["fp64_solve_seconds"] = round(sum(r["fp64_seconds"] for r in rows), 3)
         summ["fp64_iters_total"] = int(sum(r["fp64_iters"] for r in rows))
         summ["speedup"] = round(summ["fp64_solve_seconds"] / summ["solve_seconds"], 3)
         summ["max_dvel_rel_final"] = rows[-1]["max_dvel_rel"]
+        if P is not None:
+            summ["prev_speedup"] = round(summ["fp64_solve_seconds"] / summ["prev_solve_seconds"], 3)
     print(json.dumps(summ), flush=True)
 
 

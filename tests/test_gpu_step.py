@@ -179,3 +179,38 @@ def test_step_rhs_output(lib):
     b = oracle.rhs_prepare(-(rho * h / dt) * oracle.divergence(n, ud, vd, wd), 0)
     got = host(S.rhs)
     assert np.abs(got - b).max() <= 1e-8 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("precision,formulation,bar", [("fp64", "pinned", 1e-8), ("mixed", "projected", 1e-7)])
+def test_previous_pressure_guess(lib, precision, formulation, bar):
+    """Pressure solve started from the previous step's pressure: the same
+    steps as the oracle's zero-guess ones to the parity bar, and fewer CG
+    iterations than the library's own zero-guess run from step 2 on."""
+    n, nu, dt = 16, 0.01, 0.005
+    S = lib.State(n, nu=nu, lid_u=1.0)
+    Z = lib.State(n, nu=nu, lid_u=1.0)
+    R = oracle.State(n, nu=nu, lid=1.0)
+    it_prev, it_zero = [], []
+    for s in range(10):
+        info = lib.step(S, dt, tol=1e-10, precision=precision, formulation=formulation, guess="previous")
+        zinfo = lib.step(Z, dt, tol=1e-10, precision=precision, formulation=formulation)
+        it, rr, st = oracle.step(R, dt, tol=1e-10)
+        assert st == oracle.OK and info["status"] == 0 and info["rel_residual"] <= 1e-10
+        if s > 0:
+            assert info["init_residual"] < 1.0  # the previous pressure is a better start than zero
+        it_prev.append(info["iters"])
+        it_zero.append(zinfo["iters"])
+        sc = vel_scale(R)
+        assert rel(host(S.u), R.u, sc) <= bar and rel(host(S.v), R.v, sc) <= bar, s
+        assert rel(host(S.w), R.w, sc) <= bar, s
+        assert rel(mr(host(S.p)), mr(R.p)) <= bar, s
+    assert sum(it_prev[1:]) < sum(it_zero[1:])
+
+
+def test_previous_guess_validation(lib):
+    S = lib.State(8, nu=0.01, lid_u=1.0)
+    net = lib.Net()
+    with pytest.raises(lib.CfdError):
+        lib.step(S, 0.005, net=net, guess="previous")
+    with pytest.raises(ValueError):
+        lib.step(S, 0.005, guess="last")
