@@ -13,6 +13,11 @@ Functions and the passage each follows:
                       integer-stencil / pinned-cell reading.
 * ``spmv``, ``dot`` - Table 1 kernels ``spmv`` and ``dot``.
 * ``cg``            - Sec. 3.1 conjugate-gradient solve (no preconditioner).
+* ``order``, ``dic_factor``, ``dic_apply``, ``pcg`` - Sec. 3.1 preconditioned
+                      CG with the DIC or Jacobi preconditioner; DIC's
+                      recurrences follow an elimination order (natural, or
+                      red-black: the order in which they run in parallel,
+                      cf. Sec. 3.3 on DIC's loop dependencies).
 * ``step``          - Sec. 3.1 fractional step (forces, semi-Lagrangian
                       advection, pressure correction) on the staggered grid,
                       plus explicit viscosity (Sec. 5 future-work item).
@@ -65,6 +70,12 @@ def _load():
         lib.ora_rhs_prepare.argtypes = [i64, vp, i64]
         lib.ora_cg.restype = i32
         lib.ora_cg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp]
+        lib.ora_order.argtypes = [i32, i32, i32, i32, vp, vp]
+        lib.ora_dic_factor.restype = i32
+        lib.ora_dic_factor.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+        lib.ora_dic_apply.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.ora_pcg.restype = i32
+        lib.ora_pcg.argtypes = [i64, vp, vp, vp, vp, vp, dbl, i32, i32, vp, vp, vp, vp, vp]
         lib.ora_advect.restype = None
         lib.ora_advect.argtypes = [i32, i32, i32, dbl, dbl, dbl, vp, vp, vp, vp, vp, vp]
         lib.ora_diffuse.restype = None
@@ -168,6 +179,57 @@ def cg(A: Csr, b, x0=None, tol: float = 1e-10, max_iters: int = 100000):
         x0p = _p(x0)
     st = _load().ora_cg(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), x0p, tol,
                         max_iters, _p(x), ctypes.byref(it), ctypes.byref(rr))
+    return x, it.value, rr.value, st
+
+
+PRECOND = {"none": 0, "jacobi": 1, "dic": 2}
+
+
+def order(grid, redblack: bool):
+    """Elimination order: (ord, pos) with ord[t] = cell at position t."""
+    nx, ny, nz = _dims(grid)
+    n = nx * ny * nz
+    ordv = np.zeros(n, dtype=np.int64)
+    pos = np.zeros(n, dtype=np.int64)
+    _load().ora_order(nx, ny, nz, int(bool(redblack)), _p(ordv), _p(pos))
+    return ordv, pos
+
+
+def dic_factor(A: Csr, redblack: bool = True):
+    """DIC pivots d (diag(M) = diag(A)); raises if a pivot is not positive."""
+    ordv, pos = order(A.dims, redblack)
+    d = np.zeros(A.n)
+    if _load().ora_dic_factor(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(ordv), _p(pos), _p(d)) != 0:
+        raise ValueError("DIC: non-positive pivot")
+    return d
+
+
+def dic_apply(A: Csr, d, r, redblack: bool = True):
+    """z = M^{-1} r for the DIC preconditioner M = (D+L) D^{-1} (D+U)."""
+    ordv, pos = order(A.dims, redblack)
+    r = _f64(r)
+    d = _f64(d)
+    z = np.zeros(A.n)
+    work = np.zeros(A.n)
+    _load().ora_dic_apply(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(ordv), _p(pos), _p(d), _p(r), _p(z),
+                          _p(work))
+    return z
+
+
+def pcg(A: Csr, b, x0=None, tol: float = 1e-10, max_iters: int = 100000, precond: str = "dic",
+        redblack: bool = True):
+    """Preconditioned CG.  Returns (x, iters, relres, status)."""
+    b = _f64(b)
+    x = np.zeros(A.n)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    ordv, pos = order(A.dims, redblack)
+    x0p = None
+    if x0 is not None:
+        x0 = _f64(x0)
+        x0p = _p(x0)
+    st = _load().ora_pcg(A.n, _p(A.row_ptr), _p(A.col), _p(A.val), _p(b), x0p, tol, max_iters,
+                         PRECOND[precond], _p(ordv), _p(pos), _p(x), ctypes.byref(it), ctypes.byref(rr))
     return x, it.value, rr.value, st
 
 

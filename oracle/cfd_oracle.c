@@ -221,6 +221,166 @@ out:
 }
 
 /* ------------------------------------------------------------------ */
+/* Preconditioned CG (Sec. 3.1: PCG with a DIC or a Jacobi              */
+/* preconditioner; Sec. 3.3: DIC's recurrences run in a fixed order)    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Elimination order of the cells.  redblack = 0: natural (cell index);
+ * redblack = 1: the cells with i+j+k even ("red") first, then the others,
+ * each colour in cell-index order.  ord[t] is the cell at position t and
+ * pos[m] the position of cell m.
+ */
+void ora_order(int nx, int ny, int nz, int redblack, int64_t *ord, int64_t *pos) {
+    int64_t n = (int64_t)nx * ny * nz, t = 0;
+    for (int pass = 0; pass < (redblack ? 2 : 1); ++pass)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    if (redblack && ((i + j + k) & 1) != pass) continue;
+                    int64_t m = cell(i, j, k, nx, ny);
+                    ord[t] = m;
+                    pos[m] = t;
+                    ++t;
+                }
+    (void)n;
+}
+
+/*
+ * Diagonal-based incomplete Cholesky: M = (D + L) D^{-1} (D + U), where L
+ * and U hold the entries a_mj of A whose cell j comes before / after m in
+ * the order, and D is chosen so that diag(M) = diag(A):
+ *   d_m = a_mm - sum_{j before m} a_mj^2 / d_j,
+ * evaluated along the order.  Returns 0, or -1 if a pivot is not positive.
+ */
+int ora_dic_factor(int64_t n, const int32_t *rp, const int32_t *col, const double *val,
+                   const int64_t *ord, const int64_t *pos, double *d) {
+    for (int64_t t = 0; t < n; ++t) {
+        int64_t m = ord[t];
+        double dm = 0.0, s = 0.0;
+        for (int64_t e = rp[m]; e < rp[m + 1]; ++e) {
+            int64_t j = col[e];
+            if (j == m) dm += val[e];
+            else if (pos[j] < t) s += val[e] * val[e] / d[j];
+        }
+        d[m] = dm - s;
+        if (!(d[m] > 0.0)) return -1;
+    }
+    return 0;
+}
+
+/* z = M^{-1} r: forward substitution (D + L) w = r along the order, then
+ * backward substitution (D + U) z = D w against it (work: n doubles). */
+void ora_dic_apply(int64_t n, const int32_t *rp, const int32_t *col, const double *val,
+                   const int64_t *ord, const int64_t *pos, const double *d,
+                   const double *r, double *z, double *work) {
+    double *w = work;
+    for (int64_t t = 0; t < n; ++t) {
+        int64_t m = ord[t];
+        double s = r[m];
+        for (int64_t e = rp[m]; e < rp[m + 1]; ++e)
+            if (pos[col[e]] < t) s -= val[e] * w[col[e]];
+        w[m] = s / d[m];
+    }
+    for (int64_t t = n - 1; t >= 0; --t) {
+        int64_t m = ord[t];
+        double s = 0.0;
+        for (int64_t e = rp[m]; e < rp[m + 1]; ++e)
+            if (pos[col[e]] > t) s += val[e] * z[col[e]];
+        z[m] = w[m] - s / d[m];
+    }
+}
+
+enum { ORA_PRECOND_NONE = 0, ORA_PRECOND_JACOBI = 1, ORA_PRECOND_DIC = 2 };
+
+/* z = M^{-1} r for the chosen preconditioner (Jacobi: M = diag(A)). */
+static void precond_apply(int kind, int64_t n, const int32_t *rp, const int32_t *col, const double *val,
+                          const int64_t *ord, const int64_t *pos, const double *d,
+                          const double *r, double *z, double *work) {
+    if (kind == ORA_PRECOND_DIC) {
+        ora_dic_apply(n, rp, col, val, ord, pos, d, r, z, work);
+    } else if (kind == ORA_PRECOND_JACOBI) {
+        for (int64_t i = 0; i < n; ++i) z[i] = r[i] / d[i];
+    } else {
+        memcpy(z, r, sizeof(double) * n);
+    }
+}
+
+/*
+ * Preconditioned CG on A x = b, same contract as ora_cg (stop on the
+ * recursive ||r|| <= tol*||b||, confirm on the true residual, restart from
+ * it if the confirmation fails).  kind: ORA_PRECOND_*; ord/pos: elimination
+ * order for DIC (ignored otherwise).  Returns ORA_EBREAKDOWN also when the
+ * DIC factorisation meets a non-positive pivot or r^T z <= 0.
+ */
+int ora_pcg(int64_t n, const int32_t *rp, const int32_t *col, const double *val,
+            const double *b, const double *x0, double tol, int max_iters, int kind,
+            const int64_t *ord, const int64_t *pos, double *x, int *iters, double *relres) {
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    double *d = (double *)malloc(sizeof(double) * n);
+    double *work = (double *)malloc(sizeof(double) * n);
+    int status = ORA_OK, k = 0;
+    double bnorm = sqrt(ora_dot(n, b, b));
+    if (x0) memcpy(x, x0, sizeof(double) * n); else memset(x, 0, sizeof(double) * n);
+    *iters = 0;
+    if (!isfinite(bnorm)) { status = ORA_ENONFINITE; *relres = NAN; goto out; }
+    if (bnorm == 0.0) { memset(x, 0, sizeof(double) * n); *relres = 0.0; goto out; }
+    if (kind == ORA_PRECOND_DIC) {
+        if (ora_dic_factor(n, rp, col, val, ord, pos, d) != 0) { status = ORA_EBREAKDOWN; goto fin; }
+    } else if (kind == ORA_PRECOND_JACOBI) {
+        for (int64_t i = 0; i < n; ++i) {
+            d[i] = 0.0;
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (col[e] == i) d[i] += val[e];
+            if (!(d[i] > 0.0)) { status = ORA_EBREAKDOWN; goto fin; }
+        }
+    }
+
+    residual(n, rp, col, val, b, x, r);
+    if (!isfinite(ora_dot(n, r, r))) { status = ORA_ENONFINITE; goto fin; }
+    if (sqrt(ora_dot(n, r, r)) <= tol * bnorm) goto fin;
+    precond_apply(kind, n, rp, col, val, ord, pos, d, r, z, work);
+    double rho = ora_dot(n, r, z);
+    memcpy(p, z, sizeof(double) * n);
+    for (;;) {
+        if (k >= max_iters) { status = ORA_ENOCONV; break; }
+        if (!(rho > 0.0)) { status = ORA_EBREAKDOWN; break; }
+        ora_spmv(n, rp, col, val, p, q);
+        double pq = ora_dot(n, p, q);
+        ++k;
+        if (!(pq > 0.0) || !isfinite(pq)) { status = ORA_EBREAKDOWN; break; }
+        double alpha = rho / pq;
+        axpy(n, alpha, p, x);
+        axpy(n, -alpha, q, r);
+        double rr = ora_dot(n, r, r);
+        if (!isfinite(rr)) { status = ORA_ENONFINITE; break; }
+        if (sqrt(rr) <= tol * bnorm) {
+            residual(n, rp, col, val, b, x, r);
+            if (sqrt(ora_dot(n, r, r)) <= tol * bnorm) break;
+            precond_apply(kind, n, rp, col, val, ord, pos, d, r, z, work);
+            rho = ora_dot(n, r, z);
+            memcpy(p, z, sizeof(double) * n);
+            continue;
+        }
+        precond_apply(kind, n, rp, col, val, ord, pos, d, r, z, work);
+        double rho_new = ora_dot(n, r, z);
+        double beta = rho_new / rho;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+fin:
+    residual(n, rp, col, val, b, x, r);
+    *relres = sqrt(ora_dot(n, r, r)) / bnorm;
+out:
+    *iters = k;
+    free(r); free(z); free(p); free(q); free(d); free(work);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
 /* One fractional time step on the MAC grid (Sec. 3.1)                  */
 /* ------------------------------------------------------------------ */
 /*
