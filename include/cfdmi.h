@@ -109,6 +109,7 @@ typedef struct cfd_net *cfd_net_t;
 enum { CFD_PREC_FP64 = 0, CFD_PREC_MIXED = 1 };
 enum { CFD_FORM_PINNED = 0, CFD_FORM_PROJECTED = 1 };
 enum { CFD_GUESS_ZERO = 0, CFD_GUESS_PREVIOUS = 1 };
+enum { CFD_PRECOND_NONE = 0, CFD_PRECOND_DIC_RB = 1 };
 
 typedef struct cfd_solve_opts {
     int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout.
@@ -142,6 +143,23 @@ typedef struct cfd_solve_opts {
                             paper's pressure is a field carried from step to
                             step, starting uniform, Sec. 3); CFD_EINVAL
                             together with `net`.                             */
+    int32_t precond;     /* CFD_PRECOND_NONE: plain CG (the default).
+                            CFD_PRECOND_DIC_RB: CG preconditioned with the
+                            paper's diagonal-based incomplete Cholesky
+                            factor (Sec. 3.1), eliminating the cells in
+                            red-black order (i+j+k even first) so that its
+                            recurrences run in parallel (the dependency
+                            Sec. 3.3 names).  Computed in the equivalent form
+                            of Jacobi-preconditioned CG on the black cells'
+                            Schur complement S = D_b - B^T D_r^{-1} B, the
+                            red cells recovered at the end; `iters` counts
+                            products with S, and the stopping test is the
+                            same ||b - A x|| <= tol ||b||.  Both precisions
+                            and formulations, x0 and the network apply; the
+                            red-black copy of the matrix (float64 and
+                            float32) is built on the first such solve of
+                            each formulation and kept with the handle.      */
+    int32_t reserved_;
 } cfd_solve_opts;
 
 typedef struct cfd_solve_info {

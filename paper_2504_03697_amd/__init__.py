@@ -22,6 +22,7 @@ from ._lib import CfdError, CfdGrid, CfdSolveInfo, CfdSolveOpts, CfdState, check
 
 PREC = {"fp64": 0, "mixed": 1}
 FORM = {"pinned": 0, "projected": 1}
+PRECOND = {"none": 0, "dic": 1}
 
 
 def _torch():
@@ -118,19 +119,22 @@ def rhs_prepare(A: Csr, b):
     return b
 
 
-def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned"):
+def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned",
+               precond="none"):
+    """cfd_solve_opts; precond "dic" = the DIC preconditioner in red-black order."""
     return CfdSolveOpts(PREC[precision] if isinstance(precision, str) else int(precision), int(max_iters),
                         float(ru_delta), net.handle if net is not None else None, int(chunk), int(bool(timing)),
-                        FORM[formulation] if isinstance(formulation, str) else int(formulation), 0)
+                        FORM[formulation] if isinstance(formulation, str) else int(formulation), 0,
+                        PRECOND[precond] if isinstance(precond, str) else int(precond), 0)
 
 
 def solve(A: Csr, b, x0=None, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0,
-          chunk=0, timing=False, x=None, raise_on_error=True, formulation="pinned"):
+          chunk=0, timing=False, x=None, raise_on_error=True, formulation="pinned", precond="none"):
     """Solve A x = b on the device.  Returns (x, info dict)."""
     torch = _torch()
     if x is None:
         x = torch.empty(A.n, dtype=torch.float64, device=b.device)
-    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing, formulation)
+    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing, formulation, precond)
     info = CfdSolveInfo()
     rc = load().cfd_solve(A.handle, _ptr(b, torch.float64, A.n, "b"), _ptr(x0, torch.float64, A.n, "x0"),
                           float(tol), ctypes.byref(opts), _ptr(x, torch.float64, A.n, "x"),
@@ -171,10 +175,10 @@ class State:
 
 
 def step(S: State, dt, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0, chunk=0,
-         formulation="pinned", guess="zero"):
+         formulation="pinned", guess="zero", precond="none"):
     """One time step (cfd_step).  guess: "zero" (or the network's prediction
     when net is given) or "previous" (start from the pressure in S.p)."""
-    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, False, formulation)
+    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, False, formulation, precond)
     if guess not in ("zero", "previous"):
         raise ValueError("guess must be 'zero' or 'previous'")
     opts.step_guess = 1 if guess == "previous" else 0

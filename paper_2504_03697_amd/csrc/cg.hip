@@ -115,10 +115,14 @@ struct Workspace {
     CgState *host = nullptr; // pinned, 2 entries
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evc[2] = {nullptr, nullptr};
     std::vector<hipEvent_t> ta, tb;
+    struct RbMatrix *rb[2] = {nullptr, nullptr};  // red-black matrices (pinned, projected)
 };
+
+void rb_free(struct RbMatrix *m);
 
 void workspace_free(Workspace *ws) {
     if (!ws) return;
+    for (RbMatrix *m : ws->rb) rb_free(m);
     double *dd[] = {ws->r, ws->p0, ws->p1, ws->q, ws->y, ws->c, ws->part};
     for (double *p : dd) if (p) (void)hipFree(p);
     float *ff[] = {ws->r32, ws->q32};
@@ -770,6 +774,9 @@ static const Grids &solver_grids() {
     return g;
 }
 
+static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts &opts,
+                         double *x, cfd_solve_info *info, hipStream_t s);
+
 static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts *o,
                       double *x, cfd_solve_info *info, hipStream_t s) {
     cfd_solve_opts opts{};
@@ -785,6 +792,9 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     if (opts.formulation != CFD_FORM_PINNED && opts.formulation != CFD_FORM_PROJECTED)
         return fail(CFD_EINVAL, "cfd_solve: unknown formulation");
     const bool proj = opts.formulation == CFD_FORM_PROJECTED;
+    if (opts.precond != CFD_PRECOND_NONE && opts.precond != CFD_PRECOND_DIC_RB)
+        return fail(CFD_EINVAL, "cfd_solve: unknown preconditioner");
+    if (opts.precond == CFD_PRECOND_DIC_RB) return rb_solve_impl(A, b, x0, tol, opts, x, info, s);
     int rc = ensure_workspace(A, !mixed, mixed, opts.net != nullptr, proj);
     if (rc != CFD_OK) return rc;
     Workspace *w = A->ws;
@@ -945,6 +955,924 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     if (inf.status != CFD_OK) {
         const char *what = inf.status == CFD_ENOCONV ? "max_iters reached"
                          : inf.status == CFD_EBREAKDOWN ? "breakdown: p^T A p <= 0"
+                         : inf.status == CFD_ENONFINITE ? "non-finite value in the solve"
+                                                        : "solver error";
+        return fail(inf.status, std::string("cfd_solve: ") + what);
+    }
+    return CFD_OK;
+}
+
+// ================================================================ preconditioned solve
+//
+// The paper's PCG uses a diagonal-based incomplete Cholesky preconditioner
+// (Sec. 3.1): M = (D + L) D^{-1} (D + U), L and U the entries of A before and
+// after each row in the elimination order, D chosen so that diag(M) =
+// diag(A).  Its recurrences follow that order, which keeps the paper's
+// version serial (Sec. 3.3).  Here the order is red-black (cells with i+j+k
+// even first).  A 7-point cell only neighbours cells of the other colour, so
+// the red block of A is diagonal: the red pivots are a_rr and the black ones
+// the diagonal of the Schur complement S = D_b - B^T D_r^{-1} B.  In this
+// order M^{-1} A is similar to diag(I, D_S^{-1/2} S D_S^{-1/2}) (Eisenstat's
+// form of the preconditioned operator), so PCG with M is Jacobi-
+// preconditioned CG with S on the black unknowns, the red ones following
+// from x_r = D_r^{-1} (b_r - B x_b).  That is what runs: per iteration one
+// sweep over the red rows (y = D_r^{-1} B p) and one over the black rows
+// (q = D_b p - B^T y), each over half of the matrix, on black-length
+// vectors.  With x_r recovered the red rows of b - A x vanish, so the full
+// residual is the Schur residual and the stopping test is unchanged.
+//
+// The matrix is stored once more in red-black order (cfd_csr handle, built
+// on the first preconditioned solve of each formulation): perm/iperm map
+// natural <-> red-black indices, red rows first, and each row holds its
+// diagonal entry first.
+
+struct RbMatrix {
+    int64_t n = 0, nr = 0, nnz = 0;
+    int gmax = 0;
+    int32_t *perm = nullptr, *iperm = nullptr;  // natural -> red-black, and back
+    int32_t *rp = nullptr, *col = nullptr;      // CSR in red-black order, diagonal first
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+    double *d64 = nullptr;                      // diagonal of S (black rows)
+    float *d32 = nullptr;
+    // solve buffers; black length unless noted
+    double *bp = nullptr;                       // right-hand side in red-black order (n)
+    double *bS = nullptr, *xb = nullptr, *r64 = nullptr;
+    double *y64 = nullptr, *yb = nullptr;       // red length
+    double *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
+    float *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *y32 = nullptr;  // y32: red length
+    double *part = nullptr;                     // 7 * gmax partial sums
+    struct RbState *S = nullptr, *host = nullptr;
+};
+
+// Control state of the preconditioned solve: the CG state plus what the
+// black sweep needs from the red one of the same iteration.
+struct RbState {
+    CgState cg;
+    double cf;      // direction coefficient of the iteration in progress
+    double inv_s;   // 1 / scale of a restart in progress (mixed)
+    int32_t imode;  // mode of the iteration in progress
+    int32_t pad_;
+};
+
+void rb_free(RbMatrix *m) {
+    if (!m) return;
+    void *pp[] = {m->perm, m->iperm, m->rp, m->col, m->v64, m->v32, m->d64, m->d32, m->bp, m->bS, m->xb,
+                  m->r64, m->y64, m->yb, m->z64, m->p64[0], m->p64[1], m->q64, m->z32, m->p32[0], m->p32[1],
+                  m->q32, m->y32, m->part, m->S};
+    for (void *p : pp) if (p) (void)hipFree(p);
+    if (m->host) (void)hipHostFree(m->host);
+    delete m;
+}
+
+// Matrix entries of row p (cell m) in red-black order: the diagonal, then
+// the in-domain neighbours in the order -z, -y, -x, +x, +y, +z.  pin >= 0:
+// the pinned matrix (unit row at pin, pin column dropped); pin < 0: the
+// singular Neumann matrix.
+__global__ void __launch_bounds__(kBlock) rb_fill(int64_t n, int nx, int ny, int nz, int64_t pin,
+                                                  const int32_t *perm, const int32_t *iperm, const int32_t *rp,
+                                                  int32_t *col, double *v64, float *v32) {
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
+        const int64_t m = iperm[p];
+        int64_t e = rp[p];
+        if (m == pin) {
+            col[e] = (int32_t)p;
+            v64[e] = 1.0;
+            v32[e] = 1.0f;
+            continue;
+        }
+        const int64_t nxny = (int64_t)nx * ny;
+        const int i = (int)(m % nx), j = (int)((m / nx) % ny), k = (int)(m / nxny);
+        const int64_t cand[6] = {k > 0 ? m - nxny : -1, j > 0 ? m - nx : -1, i > 0 ? m - 1 : -1,
+                                 i < nx - 1 ? m + 1 : -1, j < ny - 1 ? m + nx : -1, k < nz - 1 ? m + nxny : -1};
+        int deg = 0;
+        for (int q = 0; q < 6; ++q) deg += cand[q] >= 0;
+        col[e] = (int32_t)p;
+        v64[e] = (double)deg;
+        v32[e] = (float)deg;
+        ++e;
+        for (int q = 0; q < 6; ++q) {
+            if (cand[q] < 0 || cand[q] == pin) continue;
+            col[e] = perm[cand[q]];
+            v64[e] = -1.0;
+            v32[e] = -1.0f;
+            ++e;
+        }
+    }
+}
+
+// Diagonal of the Schur complement for the black rows p in [nr, n):
+// a_pp - sum over the row's (red) neighbours j of a_pj^2 / a_jj.  In the
+// singular Neumann matrix of a grid only 2 or 3 cells long in a single
+// direction, a black cell between two end cells has a vanishing Schur row
+// (S is positive semidefinite, so a zero diagonal means a zero row); its
+// Jacobi scale is then 1, which leaves that unknown at its initial value.
+__global__ void __launch_bounds__(kBlock) rb_schur_diag(int64_t n, int64_t nr, const int32_t *rp, const int32_t *col,
+                                                        const double *v64, double *d64, float *d32) {
+    for (int64_t p = nr + (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
+        double d = v64[rp[p]];
+        for (int32_t e = rp[p] + 1; e < rp[p + 1]; ++e) d -= v64[e] * v64[e] / v64[rp[col[e]]];
+        if (!(d > 0.0)) d = 1.0;
+        d64[p - nr] = d;
+        d32[p - nr] = (float)d;
+    }
+}
+
+// Build the red-black matrix of A (proj: the Neumann matrix, else the pinned
+// one).  The permutation and the row pointers are computed on the host (one
+// pass over the cells), the entries on the device.
+static int rb_build(cfd_csr_t A, bool proj, int gmax, hipStream_t s, RbMatrix **out) {
+    const int nx = A->nx, ny = A->ny, nz = A->nz;
+    const int64_t n = A->n, nxny = (int64_t)nx * ny;
+    const int64_t pin = proj ? -1 : A->pin;
+    std::vector<int32_t> perm(n), iperm(n), rp(n + 1);
+    int64_t nr = 0;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) nr += ((i + j + k) & 1) == 0;
+    {
+        int64_t rc = 0, bc = nr, m = 0;
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i, ++m) {
+                    const int64_t p = ((i + j + k) & 1) == 0 ? rc++ : bc++;
+                    perm[m] = (int32_t)p;
+                    iperm[p] = (int32_t)m;
+                }
+    }
+    const int64_t pin_nb[6] = {pin >= 0 ? pin - nxny : -2, pin >= 0 ? pin - nx : -2, pin - 1, pin + 1,
+                               pin >= 0 ? pin + nx : -2, pin >= 0 ? pin + nxny : -2};
+    int64_t e = 0;
+    rp[0] = 0;
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t m = iperm[p];
+        int64_t len;
+        if (m == pin) {
+            len = 1;
+        } else {
+            const int i = (int)(m % nx), j = (int)((m / nx) % ny), k = (int)(m / nxny);
+            const int64_t cand[6] = {k > 0 ? m - nxny : -1, j > 0 ? m - nx : -1, i > 0 ? m - 1 : -1,
+                                     i < nx - 1 ? m + 1 : -1, j < ny - 1 ? m + nx : -1, k < nz - 1 ? m + nxny : -1};
+            len = 1;
+            for (int q = 0; q < 6; ++q) len += cand[q] >= 0 && cand[q] != pin;
+        }
+        (void)pin_nb;
+        e += len;
+        if (e > (int64_t)INT32_MAX - kPad) return fail(CFD_EINVAL, "cfd_solve: red-black matrix exceeds int32 indexing");
+        rp[p + 1] = (int32_t)e;
+    }
+    RbMatrix *M = new RbMatrix();
+    M->n = n;
+    M->nr = nr;
+    M->nnz = e;
+    M->gmax = gmax;
+    hipError_t h = hipSuccess;
+    if (h == hipSuccess) h = alloc(&M->perm, n);
+    if (h == hipSuccess) h = alloc(&M->iperm, n);
+    if (h == hipSuccess) h = alloc(&M->rp, n + 1);
+    if (h == hipSuccess) h = alloc(&M->col, e + kPad);
+    if (h == hipSuccess) h = alloc(&M->v64, e + kPad);
+    if (h == hipSuccess) h = alloc(&M->v32, e + kPad);
+    if (h == hipSuccess) h = alloc(&M->d64, n - nr);
+    if (h == hipSuccess) h = alloc(&M->d32, n - nr);
+    if (h == hipSuccess) h = hipMemcpy(M->perm, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+    if (h == hipSuccess) h = hipMemcpy(M->iperm, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+    if (h == hipSuccess) h = hipMemcpy(M->rp, rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice);
+    if (h == hipSuccess) h = hipMemsetAsync(M->col + e, 0, sizeof(int32_t) * kPad, s);
+    if (h == hipSuccess) h = hipMemsetAsync(M->v64 + e, 0, sizeof(double) * kPad, s);
+    if (h == hipSuccess) h = hipMemsetAsync(M->v32 + e, 0, sizeof(float) * kPad, s);
+    if (h != hipSuccess) {
+        rb_free(M);
+        return hip_fail(h, "cfd_solve: red-black matrix");
+    }
+    const unsigned g = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
+    hipLaunchKernelGGL(rb_fill, dim3(g), dim3(kBlock), 0, s, n, nx, ny, nz, pin, (const int32_t *)M->perm,
+                       (const int32_t *)M->iperm, (const int32_t *)M->rp, M->col, M->v64, M->v32);
+    hipLaunchKernelGGL(rb_schur_diag, dim3(g), dim3(kBlock), 0, s, n, nr, (const int32_t *)M->rp,
+                       (const int32_t *)M->col, (const double *)M->v64, M->d64, M->d32);
+    h = hipGetLastError();
+    if (h != hipSuccess) {
+        rb_free(M);
+        return hip_fail(h, "cfd_solve: red-black matrix");
+    }
+    *out = M;
+    return CFD_OK;
+}
+
+static int rb_buffers(RbMatrix *M, bool mixed) {
+    const int64_t nb = M->n - M->nr, nr = M->nr;
+    hipError_t h = hipSuccess;
+    if (h == hipSuccess) h = alloc(&M->bp, M->n);
+    if (h == hipSuccess) h = alloc(&M->bS, nb);
+    if (h == hipSuccess) h = alloc(&M->xb, nb);
+    if (h == hipSuccess) h = alloc(&M->r64, nb);
+    if (h == hipSuccess) h = alloc(&M->y64, nr);
+    if (h == hipSuccess) h = alloc(&M->yb, nr);
+    if (h == hipSuccess) h = alloc(&M->part, (int64_t)M->gmax * 7);
+    if (h == hipSuccess) h = alloc(&M->S, 2);
+    if (h == hipSuccess && !M->host) h = hipHostMalloc((void **)&M->host, sizeof(RbState) * 2, 0);
+    if (mixed) {
+        if (h == hipSuccess) h = alloc(&M->z32, nb);
+        if (h == hipSuccess) h = alloc(&M->p32[0], nb);
+        if (h == hipSuccess) h = alloc(&M->p32[1], nb);
+        if (h == hipSuccess) h = alloc(&M->q32, nb);
+        if (h == hipSuccess) h = alloc(&M->y32, nr);
+    } else {
+        if (h == hipSuccess) h = alloc(&M->z64, nb);
+        if (h == hipSuccess) h = alloc(&M->p64[0], nb);
+        if (h == hipSuccess) h = alloc(&M->p64[1], nb);
+        if (h == hipSuccess) h = alloc(&M->q64, nb);
+    }
+    if (h != hipSuccess) return hip_fail(h, "cfd_solve: red-black solver buffers");
+    return CFD_OK;
+}
+
+struct RbArgs {
+    int64_t n, nr, nb;
+    const int32_t *rp, *col;
+    const double *v64;
+    const float *v32;
+    const double *d64;
+    const float *d32;
+    const int32_t *perm, *iperm;
+    double tol, ru_delta;
+    int32_t max_iters;
+    int32_t G1, G2, Gv;     // red sweeps, black sweeps, black vector kernels
+    int32_t Gw, Gs;         // partial counts of the warm-start and right-hand-side sums
+    int64_t pin;
+    int32_t proj, nnb;
+    int64_t nbr[6];         // natural indices of the pin's neighbours
+    const double *b;
+    double *x;
+    const double *x0, *y;   // initial guess or warm-start prediction (NULL = none)
+    double *bp, *bS, *xb, *r64, *y64, *yb;
+    double *z64, *p64a, *p64b, *q64;
+    float *z32, *p32a, *p32b, *q32, *y32;
+    double *partA, *partB, *partB2, *partF, *partFp, *partFz, *partF2;
+    const double *partG1, *partG2, *partS;
+    RbState *S;
+};
+
+__device__ inline bool rb_is_pin_nb(const RbArgs &a, int64_t i) {
+    for (int q = 0; q < a.nnb; ++q)
+        if (i == a.nbr[q]) return true;
+    return false;
+}
+
+// Right-hand side in red-black order (projected: the consistent c) and the
+// initial guess's black part; partial sums of ||b||^2.
+__global__ void __launch_bounds__(kBlock) rb_rhs(RbArgs a) {
+    __shared__ double red[kBlock / 64];
+    double gamma = 0.0;
+    if (a.y) {
+        const double yay = reduce_partials(a.partG1, a.Gw, red);
+        const double by = reduce_partials(a.partG2, a.Gw, red);
+        gamma = by / yay;
+        if (!(yay > 0.0) || !std::isfinite(gamma)) gamma = 0.0;
+    }
+    const double bpin = a.b[a.pin];
+    double cpin = bpin;
+    if (a.proj) {
+        const double sb = reduce_partials(a.partS, a.Gs, red);
+        cpin = -(sb - bpin) + (double)a.nnb * bpin;
+    }
+    double bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        const double bi = a.b[i];
+        double ci = bi;
+        if (a.proj) ci = (i == a.pin) ? cpin : (rb_is_pin_nb(a, i) ? bi - bpin : bi);
+        const int64_t p = a.perm[i];
+        a.bp[p] = ci;
+        bb = fma(bi, bi, bb);
+        if (p >= a.nr) {
+            double g = 0.0;
+            if (a.y) g = (i == a.pin) ? 0.0 : gamma * a.y[i];
+            else if (a.x0) g = a.x0[i];
+            a.xb[p - a.nr] = g;
+        }
+    }
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) a.partF2[blockIdx.x] = bb;
+}
+
+// Red rows of the initial residual: y = D_r^{-1} (b_r - B x0_b) and
+// yb = D_r^{-1} b_r (for the Schur right-hand side).
+__global__ void __launch_bounds__(kBlock) rb_init_red(RbArgs a) {
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) double s_val[kSlabLds];
+    auto none = [](int64_t) { return 0; };
+    csr_sweep_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+        double acc = 0.0;
+        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], a.xb[s_col[e] - a.nr], acc);
+        const double bi = a.bp[p], di = s_val[rs];
+        a.y64[p] = (bi - acc) / di;
+        a.yb[p] = bi / di;
+    });
+}
+
+// Black rows: b_S = b_b - B^T yb and r = b_S - S x0 = b_b - D_b x0 - B^T y;
+// partial sums of ||r||^2 (all rows, and without the pin row), r^T D_S^{-1} r;
+// fresh control state.
+__global__ void __launch_bounds__(kBlock) rb_init_black(RbArgs a, int64_t t) {
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) double s_val[kSlabLds];
+    __shared__ double red[kBlock / 64];
+    double gamma = 0.0;
+    int fallback = 0;
+    if (a.y) {  // the warm-start scale, as rb_rhs applied it (reduced by every thread)
+        const double yay = reduce_partials(a.partG1, a.Gw, red);
+        const double by = reduce_partials(a.partG2, a.Gw, red);
+        gamma = by / yay;
+        if (!(yay > 0.0) || !std::isfinite(gamma)) {
+            gamma = 0.0;
+            fallback = 1;
+        }
+    }
+    double rr = 0.0, rp_ = 0.0, rz = 0.0;
+    const int64_t pin_p = a.perm[a.pin];
+    auto none = [](int64_t) { return 0; };
+    csr_sweep_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+        double sy = 0.0, syb = 0.0;
+        for (int e = rs + 1; e < re; ++e) {
+            sy = fma(s_val[e], a.y64[s_col[e]], sy);
+            syb = fma(s_val[e], a.yb[s_col[e]], syb);
+        }
+        const int64_t k = p - a.nr;
+        const double bi = a.bp[p];
+        a.bS[k] = bi - syb;
+        const double ri = bi - s_val[rs] * a.xb[k] - sy;
+        a.r64[k] = ri;
+        rr = fma(ri, ri, rr);
+        if (!(a.proj && p == pin_p)) rp_ = fma(ri, ri, rp_);
+        rz = fma(ri, ri / a.d64[k], rz);
+    });
+    rr = block_sum(rr, red);
+    rp_ = block_sum(rp_, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        a.partF[blockIdx.x] = rr;
+        a.partFp[blockIdx.x] = rp_;
+        a.partFz[blockIdx.x] = rz;
+    }
+    if (lead()) {
+        RbState ns{};
+        ns.cg.mode = MODE_INIT;
+        ns.cg.scale = 1.0;
+        ns.cg.gamma = gamma;
+        ns.cg.fallback = fallback;
+        a.S[(t + 1) & 1] = ns;
+    }
+}
+
+// Decision at the start of each red sweep (identical in every workgroup).
+// Normal mode: from the vector kernel's partial sums of ||r||^2 (r = D_S z)
+// and r^T z.  Restart (init or refresh): from the true residual's sums.
+// Mixed precision keeps z normalised by the scale s of the last true
+// residual: z_true = s z, and rho = r^T z in those units.
+template <bool MIXED>
+__device__ inline Decision rb_decide(const RbArgs &a, const CgState &st, double *red) {
+    Decision D;
+    D.stop = false;
+    D.zero_x = false;
+    D.fold = false;
+    D.beta = 0.0;
+    D.cref = 0.0;
+    D.inv_s = 1.0;
+    D.shift = 0.0;
+    CgState ns = st;
+    if (st.mode == MODE_NORMAL) {
+        const double rr = reduce_partials(a.partB, a.Gv, red);
+        const double rz = reduce_partials(a.partB2, a.Gv, red);
+        const double nr = sqrt(rr);
+        int reason = R_NONE;
+        if (!std::isfinite(rr) || !std::isfinite(rz)) reason = R_NONFINITE;
+        else if (nr * st.scale <= a.tol * st.bnorm) reason = R_CONVERGED;
+        else if (MIXED && nr < a.ru_delta * st.rmax) reason = R_REFRESH;
+        else if (st.iters >= a.max_iters) reason = R_NOCONV;
+        if (reason != R_NONE) {
+            ns.pending = 1;
+            ns.reason = reason;
+            ns.rho_new = rr;
+            D.stop = true;
+        } else {
+            D.beta = rz / st.rho;
+            ns.rho = rz;
+            ns.rmax = std::max(st.rmax, nr);
+        }
+    } else {
+        const double rr = reduce_partials(a.partF, a.G2, red);
+        const double rrp = reduce_partials(a.partFp, a.G2, red);
+        const double rz = reduce_partials(a.partFz, a.G2, red);
+        if (st.mode == MODE_INIT) ns.bnorm = sqrt(reduce_partials(a.partF2, a.Gv, red));
+        const double tr = sqrt(rr), trp = sqrt(rrp);
+        const double bn = ns.bnorm;
+        ns.reason = R_NONE;
+        ns.alpha = 0.0;
+        if (!std::isfinite(bn) || !std::isfinite(rr) || !std::isfinite(rrp) || !std::isfinite(rz)) {
+            ns.done = 1;
+            ns.status = CFD_ENONFINITE;
+            ns.relres = NAN;
+        } else if (bn == 0.0) {
+            ns.done = 1;
+            ns.status = CFD_OK;
+            ns.relres = 0.0;
+            D.zero_x = true;
+        } else {
+            ns.relres = trp / bn;
+            if (st.mode == MODE_INIT) ns.init_relres = ns.relres;
+            if (trp <= a.tol * bn) {
+                ns.done = 1;
+                ns.status = CFD_OK;
+            } else if (st.reason == R_NOCONV || st.iters >= a.max_iters) {
+                ns.done = 1;
+                ns.status = CFD_ENOCONV;
+            } else if (st.reason == R_BREAKDOWN) {
+                ns.done = 1;
+                ns.status = CFD_EBREAKDOWN;
+            } else if (st.reason == R_NONFINITE) {
+                ns.done = 1;
+                ns.status = CFD_ENONFINITE;
+            }
+        }
+        if (ns.done) {
+            D.stop = true;
+        } else if (MIXED) {
+            // restart from z = r / (s D_S) with s = ||r||, keeping the old
+            // direction: beta_true = rz / (s_old^2 rho_old), rescaled by
+            // s_old / s into the new units
+            D.inv_s = 1.0 / tr;
+            D.cref = (st.mode == MODE_INIT) ? 0.0 : rz / (st.scale * st.rho * tr);
+            ns.scale = tr;
+            ns.rho = rz / (tr * tr);
+            ns.rmax = 1.0;
+        } else {
+            D.beta = 0.0;  // float64: restart from z = D_S^{-1} r
+            ns.rho = rz;
+        }
+    }
+    D.ns = ns;
+    return D;
+}
+
+// x in natural order when the solve ends: black cells from x_b, red cells
+// x_r = D_r^{-1} (b_r - B x_b); projected formulation: shifted so that
+// x_pin = b_pin.
+__device__ inline double rb_x_at(const RbArgs &a, int64_t p) {
+    if (p >= a.nr) return a.xb[p - a.nr];
+    double acc = 0.0;
+    for (int32_t e = a.rp[p] + 1; e < a.rp[p + 1]; ++e) acc = fma(a.v64[e], a.xb[a.col[e] - a.nr], acc);
+    return (a.bp[p] - acc) / a.v64[a.rp[p]];
+}
+
+__device__ inline void rb_write_x(const RbArgs &a, bool zero_x) {
+    const double shift = (a.proj && !zero_x) ? a.b[a.pin] - rb_x_at(a, a.perm[a.pin]) : 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < a.n; p += (int64_t)gridDim.x * kBlock) {
+        const int64_t m = a.iperm[p];
+        a.x[m] = zero_x ? 0.0 : (a.proj && m == a.pin) ? a.b[a.pin] : rb_x_at(a, p) + shift;
+    }
+}
+
+// The direction at black index k: p = z + cf p_old, with z = z32/z64 in normal
+// mode and z = r64 / (s d) (mixed) or r64 / d (float64) in a restart.
+template <bool MIXED>
+struct RbDir {
+    typedef typename std::conditional<MIXED, float, double>::type VT;
+    const RbArgs &a;
+    const VT *pold;
+    VT cf;
+    double inv_s;
+    bool normal, use_p;
+    __device__ inline VT z(int64_t k) const {
+        if (normal) return MIXED ? (VT)a.z32[k] : (VT)a.z64[k];
+        return MIXED ? (VT)(a.r64[k] * inv_s / a.d64[k]) : (VT)(a.r64[k] / a.d64[k]);
+    }
+    __device__ inline VT w(int64_t k) const {
+        const VT zk = z(k);
+        return use_p ? (VT)fma(cf, pold[k], zk) : zk;
+    }
+};
+
+// Red sweep: y = D_r^{-1} B p (p formed on the fly at the black neighbours).
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
+    typedef typename std::conditional<MIXED, float, double>::type VT;
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) VT s_val[kSlabLds];
+    __shared__ double red[kBlock / 64];
+    const RbState st = a.S[t & 1];
+    RbState *out = &a.S[(t + 1) & 1];
+    if (st.cg.done || st.cg.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const Decision D = rb_decide<MIXED>(a, st.cg, red);
+    if (D.stop) {
+        if (D.ns.done) rb_write_x(a, D.zero_x);
+        if (lead()) {
+            RbState ns = st;
+            ns.cg = D.ns;
+            *out = ns;
+        }
+        return;
+    }
+    const bool normal = st.cg.mode == MODE_NORMAL;
+    const VT cf = (VT)(normal ? D.beta : (MIXED ? D.cref : 0.0));
+    if (lead()) {
+        RbState ns = st;
+        ns.cg = D.ns;
+        ns.cf = (double)cf;
+        ns.inv_s = D.inv_s;
+        ns.imode = st.cg.mode;
+        *out = ns;
+    }
+    const VT *pold = MIXED ? (const VT *)(st.cg.pcur ? a.p32b : a.p32a) : (const VT *)(st.cg.pcur ? a.p64b : a.p64a);
+    const RbDir<MIXED> dir{a, pold, cf, D.inv_s, normal, normal || st.cg.mode == MODE_REFRESH};
+    VT *y = MIXED ? (VT *)a.y32 : (VT *)a.y64;
+    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
+    auto none = [](int64_t) { return 0; };
+    csr_sweep_rows<VT>(a.rp, a.col, val, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+        VT acc = 0;
+        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], dir.w(s_col[e] - a.nr), acc);
+        y[p] = acc / s_val[rs];
+    });
+}
+
+// Black sweep: p = z + cf p_old, q = D_b p - B^T y; partial sums of p^T q.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
+    typedef typename std::conditional<MIXED, float, double>::type VT;
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) VT s_val[kSlabLds];
+    __shared__ double red[kBlock / 64];
+    const RbState st = a.S[t & 1];
+    RbState *out = &a.S[(t + 1) & 1];
+    if (st.cg.done || st.cg.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const bool normal = st.imode == MODE_NORMAL;
+    const VT *pold = MIXED ? (const VT *)(st.cg.pcur ? a.p32b : a.p32a) : (const VT *)(st.cg.pcur ? a.p64b : a.p64a);
+    VT *pnew = MIXED ? (VT *)(st.cg.pcur ? a.p32a : a.p32b) : (VT *)(st.cg.pcur ? a.p64a : a.p64b);
+    VT *q = MIXED ? (VT *)a.q32 : (VT *)a.q64;
+    VT *z = MIXED ? (VT *)a.z32 : (VT *)a.z64;
+    const VT *y = MIXED ? (const VT *)a.y32 : (const VT *)a.y64;
+    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
+    const RbDir<MIXED> dir{a, pold, (VT)st.cf, st.inv_s, normal, normal || st.imode == MODE_REFRESH};
+    double pq = 0.0;
+    auto own = [&](int64_t p) { return dir.z(p - a.nr); };
+    csr_sweep_rows<VT>(a.rp, a.col, val, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT zk) {
+        const int64_t k = p - a.nr;
+        const VT wk = dir.use_p ? (VT)fma(dir.cf, pold[k], zk) : zk;
+        VT acc = 0;
+        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], y[s_col[e]], acc);
+        const VT qk = fma(s_val[rs], wk, -acc);
+        if (!normal) z[k] = zk;
+        store_stream(pnew + k, wk);
+        store_stream(q + k, qk);
+        pq = fma((double)wk, (double)qk, pq);
+    });
+    pq = block_sum(pq, red);
+    if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
+    if (lead()) {
+        RbState ns = st;
+        ns.cg.mode = MODE_NORMAL;
+        ns.cg.iters = st.cg.iters + 1;
+        ns.cg.pcur = 1 - st.cg.pcur;
+        *out = ns;
+    }
+}
+
+// Vector kernel: alpha = rho / p^T q; z -= alpha D_S^{-1} q; x_b += s alpha p
+// (float64); partial sums of ||D_S z||^2 and z^T D_S z.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
+    typedef typename std::conditional<MIXED, float, double>::type VT;
+    __shared__ double red[kBlock / 64];
+    const RbState st = a.S[t & 1];
+    RbState *out = &a.S[(t + 1) & 1];
+    if (st.cg.done || st.cg.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const double pq = reduce_partials(a.partA, a.G2, red);
+    const double alpha = st.cg.rho / pq;
+    if (!(pq > 0.0) || !std::isfinite(alpha)) {
+        if (lead()) {
+            RbState ns = st;
+            ns.cg.pending = 1;
+            ns.cg.reason = R_BREAKDOWN;
+            *out = ns;
+        }
+        return;
+    }
+    const VT *p = MIXED ? (const VT *)(st.cg.pcur ? a.p32b : a.p32a) : (const VT *)(st.cg.pcur ? a.p64b : a.p64a);
+    const VT *q = MIXED ? (const VT *)a.q32 : (const VT *)a.q64;
+    VT *z = MIXED ? (VT *)a.z32 : (VT *)a.z64;
+    const VT *d = MIXED ? (const VT *)a.d32 : (const VT *)a.d64;
+    const VT av = (VT)alpha;
+    const double sa = st.cg.scale * alpha;
+    double rr = 0.0, rz = 0.0;
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < a.nb; k += (int64_t)gridDim.x * kBlock) {
+        const VT dk = d[k];
+        const VT zk = fma(-av, q[k] / dk, z[k]);
+        store_stream(z + k, zk);
+        store_stream(a.xb + k, fma(sa, (double)p[k], a.xb[k]));
+        const double rk = (double)dk * (double)zk;
+        rr = fma(rk, rk, rr);
+        rz = fma(rk, (double)zk, rz);
+    }
+    rr = block_sum(rr, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        a.partB[blockIdx.x] = rr;
+        a.partB2[blockIdx.x] = rz;
+    }
+    if (lead()) {
+        RbState ns = st;
+        ns.cg.alpha = alpha;
+        *out = ns;
+    }
+}
+
+// Refresh, red sweep (when a refresh is pending): y64 = D_r^{-1} B x_b.
+__global__ void __launch_bounds__(kBlock) rb_f1(RbArgs a, int64_t t) {
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) double s_val[kSlabLds];
+    const RbState st = a.S[t & 1];
+    RbState *out = &a.S[(t + 1) & 1];
+    if (lead()) *out = st;
+    if (st.cg.done || !st.cg.pending) return;
+    auto none = [](int64_t) { return 0; };
+    csr_sweep_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+        double acc = 0.0;
+        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], a.xb[s_col[e] - a.nr], acc);
+        a.y64[p] = acc / s_val[rs];
+    });
+}
+
+// Refresh, black sweep: r = b_S - S x_b = b_S - D_b x_b + B^T y64 in float64;
+// partial sums of ||r||^2 (all rows, and without the pin row), r^T D_S^{-1} r.
+__global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) double s_val[kSlabLds];
+    __shared__ double red[kBlock / 64];
+    const RbState st = a.S[t & 1];
+    RbState *out = &a.S[(t + 1) & 1];
+    if (st.cg.done || !st.cg.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const int64_t pin_p = a.perm[a.pin];
+    double rr = 0.0, rp_ = 0.0, rz = 0.0;
+    auto none = [](int64_t) { return 0; };
+    csr_sweep_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+        double acc = 0.0;
+        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], a.y64[s_col[e]], acc);
+        const int64_t k = p - a.nr;
+        const double ri = a.bS[k] - s_val[rs] * a.xb[k] + acc;
+        a.r64[k] = ri;
+        rr = fma(ri, ri, rr);
+        if (!(a.proj && p == pin_p)) rp_ = fma(ri, ri, rp_);
+        rz = fma(ri, ri / a.d64[k], rz);
+    });
+    rr = block_sum(rr, red);
+    rp_ = block_sum(rp_, red);
+    rz = block_sum(rz, red);
+    if (threadIdx.x == 0) {
+        a.partF[blockIdx.x] = rr;
+        a.partFp[blockIdx.x] = rp_;
+        a.partFz[blockIdx.x] = rz;
+    }
+    if (lead()) {
+        RbState ns = st;
+        ns.cg.pending = 0;
+        ns.cg.mode = MODE_REFRESH;
+        ns.cg.updates = st.cg.updates + 1;
+        *out = ns;
+    }
+}
+
+// Host driver of the preconditioned solve (options already validated).
+static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts &opts,
+                         double *x, cfd_solve_info *info, hipStream_t s) {
+    const bool mixed = opts.precision == CFD_PREC_MIXED;
+    const bool proj = opts.formulation == CFD_FORM_PROJECTED;
+    const int max_iters = opts.max_iters > 0 ? opts.max_iters : 100000;
+    const double delta = opts.ru_delta > 0.0 ? opts.ru_delta : 0.1;
+    const int K = opts.chunk > 0 ? opts.chunk : 16;
+    int rc = ensure_workspace(A, false, false, opts.net != nullptr, false);
+    if (rc != CFD_OK) return rc;
+    Workspace *w = A->ws;
+    RbMatrix *&M = w->rb[proj ? 1 : 0];
+    if (!M) {
+        rc = rb_build(A, proj, w->gmax, s, &M);
+        if (rc != CFD_OK) return rc;
+    }
+    rc = rb_buffers(M, mixed);
+    if (rc != CFD_OK) return rc;
+    const int64_t n = A->n, nr = M->nr, nb = n - nr;
+
+    // the natural-order helpers (warm-start scale, right-hand-side sum)
+    SolveArgs g{};
+    g.n = n;
+    g.rp = A->rp;
+    g.col = A->col;
+    g.v64 = A->val64;
+    g.v32 = A->val32;
+    g.pin = A->pin;
+    g.proj = proj ? 1 : 0;
+    g.nxny = (int64_t)A->nx * A->ny;
+    {
+        const int64_t p = A->pin, nx = A->nx, ny = A->ny, nz = A->nz;
+        const int64_t i = p % nx, j = (p / nx) % ny, k = p / (nx * ny);
+        const int64_t cand[6] = {k > 0 ? p - nx * ny : -1, j > 0 ? p - nx : -1, i > 0 ? p - 1 : -1,
+                                 i < nx - 1 ? p + 1 : -1, j < ny - 1 ? p + nx : -1, k < nz - 1 ? p + nx * ny : -1};
+        for (int q = 0; q < 6; ++q)
+            if (cand[q] >= 0) g.nb[g.nnb++] = cand[q];
+    }
+    g.b = b;
+    g.Gb = grid_vec(n);
+    g.Gf = grid_tiles(n, resident_per_cu(warm_gamma));
+    const int64_t gm = w->gmax;
+    g.partG1 = w->part + 4 * gm;
+    g.partG2 = w->part + 5 * gm;
+    g.partS = w->part + 8 * gm;
+
+    RbArgs a{};
+    a.n = n;
+    a.nr = nr;
+    a.nb = nb;
+    a.rp = M->rp;
+    a.col = M->col;
+    a.v64 = M->v64;
+    a.v32 = M->v32;
+    a.d64 = M->d64;
+    a.d32 = M->d32;
+    a.perm = M->perm;
+    a.iperm = M->iperm;
+    a.tol = tol;
+    a.ru_delta = delta;
+    a.max_iters = max_iters;
+    static const int k1_per_cu[2] = {resident_per_cu(rb_k1<false>), resident_per_cu(rb_k1<true>)};
+    static const int k2_per_cu[2] = {resident_per_cu(rb_k2<false>), resident_per_cu(rb_k2<true>)};
+    static const int f_per_cu = std::min(std::min(resident_per_cu(rb_f1), resident_per_cu(rb_f2)),
+                                         std::min(resident_per_cu(rb_init_red), resident_per_cu(rb_init_black)));
+    a.G1 = grid_tiles(nr, std::min(k1_per_cu[mixed], f_per_cu));
+    a.G2 = grid_tiles(nb, std::min(k2_per_cu[mixed], f_per_cu));
+    a.Gv = grid_vec(nb);
+    a.Gw = g.Gf;
+    a.Gs = g.Gb;
+    a.pin = A->pin;
+    a.proj = proj ? 1 : 0;
+    a.nnb = g.nnb;
+    for (int q = 0; q < 6; ++q) a.nbr[q] = g.nb[q];
+    a.b = b;
+    a.x = x;
+    a.x0 = x0;
+    a.y = nullptr;
+    a.bp = M->bp;
+    a.bS = M->bS;
+    a.xb = M->xb;
+    a.r64 = M->r64;
+    a.y64 = M->y64;
+    a.yb = M->yb;
+    a.z64 = M->z64;
+    a.p64a = M->p64[0];
+    a.p64b = M->p64[1];
+    a.q64 = M->q64;
+    a.z32 = M->z32;
+    a.p32a = M->p32[0];
+    a.p32b = M->p32[1];
+    a.q32 = M->q32;
+    a.y32 = M->y32;
+    a.partA = M->part;
+    a.partB = M->part + gm;
+    a.partB2 = M->part + 2 * gm;
+    a.partF = M->part + 3 * gm;
+    a.partFp = M->part + 4 * gm;
+    a.partFz = M->part + 5 * gm;
+    a.partF2 = M->part + 6 * gm;
+    a.partG1 = g.partG1;
+    a.partG2 = g.partG2;
+    a.partS = g.partS;
+    a.S = M->S;
+
+    CFD_HIP(hipEventRecord(w->ev0, s));
+    if (opts.net) {
+        cfd_grid gr{A->nx, A->ny, A->nz, A->h};
+        rc = net_predict(opts.net, &gr, b, w->y, s);
+        if (rc != CFD_OK) return rc;
+        g.y = w->y;
+        a.y = w->y;
+        hipLaunchKernelGGL(warm_gamma, dim3(g.Gf), dim3(kBlock), 0, s, g);
+    }
+    if (proj) hipLaunchKernelGGL(rhs_sum, dim3(g.Gb), dim3(kBlock), 0, s, g);
+    hipLaunchKernelGGL(rb_rhs, dim3(a.Gv), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(rb_init_red, dim3(a.G1), dim3(kBlock), 0, s, a);
+    int64_t t = 0;
+    hipLaunchKernelGGL(rb_init_black, dim3(a.G2), dim3(kBlock), 0, s, a, t);
+    ++t;
+    CFD_HIP(hipGetLastError());
+
+    const int pool = opts.timing ? 256 : 0;
+    while ((int)w->ta.size() < pool) {
+        hipEvent_t e0, e1;
+        CFD_HIP(hipEventCreate(&e0));
+        CFD_HIP(hipEventCreate(&e1));
+        w->ta.push_back(e0);
+        w->tb.push_back(e1);
+    }
+    std::vector<char> sampled, live;
+    const int64_t cap = (int64_t)max_iters + 64;
+    int64_t c = 0;
+    RbState final_state{};
+    for (;; ++c) {
+        if (c > cap) return fail(CFD_EHIP, "cfd_solve: solver control did not terminate");
+        bool smp = false;
+        for (int i = 0; i < K; ++i) {
+            const bool time_it = (i == 1 || K == 1) && c < pool;
+            smp = smp || time_it;
+            // one product with S: the red sweep and the black sweep
+            if (mixed) {
+                if (time_it)
+                    hipExtLaunchKernelGGL(rb_k1<true>, dim3(a.G1), dim3(kBlock), 0, s, w->ta[c], nullptr, 0, a, t);
+                else
+                    hipLaunchKernelGGL(rb_k1<true>, dim3(a.G1), dim3(kBlock), 0, s, a, t);
+                ++t;
+                if (time_it)
+                    hipExtLaunchKernelGGL(rb_k2<true>, dim3(a.G2), dim3(kBlock), 0, s, nullptr, w->tb[c], 0, a, t);
+                else
+                    hipLaunchKernelGGL(rb_k2<true>, dim3(a.G2), dim3(kBlock), 0, s, a, t);
+                ++t;
+                hipLaunchKernelGGL(rb_b<true>, dim3(a.Gv), dim3(kBlock), 0, s, a, t);
+            } else {
+                if (time_it)
+                    hipExtLaunchKernelGGL(rb_k1<false>, dim3(a.G1), dim3(kBlock), 0, s, w->ta[c], nullptr, 0, a, t);
+                else
+                    hipLaunchKernelGGL(rb_k1<false>, dim3(a.G1), dim3(kBlock), 0, s, a, t);
+                ++t;
+                if (time_it)
+                    hipExtLaunchKernelGGL(rb_k2<false>, dim3(a.G2), dim3(kBlock), 0, s, nullptr, w->tb[c], 0, a, t);
+                else
+                    hipLaunchKernelGGL(rb_k2<false>, dim3(a.G2), dim3(kBlock), 0, s, a, t);
+                ++t;
+                hipLaunchKernelGGL(rb_b<false>, dim3(a.Gv), dim3(kBlock), 0, s, a, t);
+            }
+            ++t;
+        }
+        hipLaunchKernelGGL(rb_f1, dim3(a.G1), dim3(kBlock), 0, s, a, t);
+        ++t;
+        hipLaunchKernelGGL(rb_f2, dim3(a.G2), dim3(kBlock), 0, s, a, t);
+        ++t;
+        CFD_HIP(hipGetLastError());
+        sampled.push_back(smp);
+        live.push_back(0);
+        const int slot = (int)(c & 1);
+        CFD_HIP(hipMemcpyAsync(&M->host[slot], &M->S[t & 1], sizeof(RbState), hipMemcpyDeviceToHost, s));
+        CFD_HIP(hipEventRecord(w->evc[slot], s));
+        if (c >= 1) {
+            const int prev = (int)((c - 1) & 1);
+            CFD_HIP(hipEventSynchronize(w->evc[prev]));
+            const RbState ps = M->host[prev];
+            live[c - 1] = !ps.cg.done;
+            if (ps.cg.done) break;
+        }
+    }
+    CFD_HIP(hipEventSynchronize(w->evc[c & 1]));
+    final_state = M->host[c & 1];
+    live[c] = !final_state.cg.done;
+    CFD_HIP(hipEventRecord(w->ev1, s));
+    CFD_HIP(hipEventSynchronize(w->ev1));
+    float ms = 0.0f;
+    CFD_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+
+    const CgState &fs = final_state.cg;
+    cfd_solve_info inf{};
+    inf.iters = fs.iters;
+    inf.updates = fs.updates;
+    inf.status = fs.done ? fs.status : CFD_EHIP;
+    inf.used_fallback = fs.fallback;
+    inf.rel_residual = fs.relres;
+    inf.init_residual = fs.init_relres;
+    inf.gamma = fs.gamma;
+    inf.seconds = ms * 1e-3;
+    double tot = 0.0;
+    int ns = 0;
+    for (int64_t i = 0; i < (int64_t)sampled.size() && i < pool; ++i) {
+        if (!sampled[i] || !live[i]) continue;
+        float e = 0.0f;
+        if (hipEventElapsedTime(&e, w->ta[i], w->tb[i]) == hipSuccess) {
+            tot += e;
+            ++ns;
+        }
+    }
+    inf.spmv_ms = ns ? tot / ns : 0.0;
+    inf.spmv_samples = ns;
+    if (info) *info = inf;
+    if (!fs.done) return fail(CFD_EHIP, "cfd_solve: solver did not finish");
+    if (inf.status != CFD_OK) {
+        const char *what = inf.status == CFD_ENOCONV ? "max_iters reached"
+                         : inf.status == CFD_EBREAKDOWN ? "breakdown: p^T S p <= 0"
                          : inf.status == CFD_ENONFINITE ? "non-finite value in the solve"
                                                         : "solver error";
         return fail(inf.status, std::string("cfd_solve: ") + what);

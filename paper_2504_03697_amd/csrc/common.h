@@ -179,6 +179,31 @@ struct SlabPipe {
         }
     }
 
+    // As fetch(), for the nr_ rows starting at row r0_ (a tile of a row range).
+    __device__ inline void fetch_range(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                       const VT *__restrict__ val, int64_t r0_, int nr_) {
+        const int tid = threadIdx.x;
+        r0 = r0_;
+        nr = nr_;
+        const int32_t e0 = rp[r0], e1 = rp[r0 + nr];
+        ea = e0 & ~3;
+        cnt = e1 - ea;
+        const i32x4 *c4 = reinterpret_cast<const i32x4 *>(col + ea);
+        const VV *v4 = reinterpret_cast<const VV *>(val + ea);
+#pragma unroll
+        for (int v = 0; v < kVecC; ++v)
+            if ((tid + v * kBlock) * 4 < cnt) rc[v] = __builtin_nontemporal_load(c4 + tid + v * kBlock);
+#pragma unroll
+        for (int v = 0; v < kVecV; ++v)
+            if ((tid + v * kBlock) * kPerV < cnt) rv[v] = __builtin_nontemporal_load(v4 + tid + v * kBlock);
+        if (tid < nr) {
+            rs = rp[r0 + tid] - ea;
+            re = rp[r0 + tid + 1] - ea;
+        } else {
+            rs = re = 0;
+        }
+    }
+
     __device__ inline void commit(int32_t *s_col, VT *s_val) const {
         const int tid = threadIdx.x;
 #pragma unroll
@@ -240,6 +265,39 @@ __device__ inline void csr_sweep_pre(const int32_t *__restrict__ rp, const int32
         __syncthreads();
         if (t + tr.step < tr.end) {
             P.fetch(rp, col, val, n, t + tr.step);
+            if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
+        }
+        if ((int)threadIdx.x < nr) body(r0 + threadIdx.x, rs, re, cur);
+        __syncthreads();
+    }
+}
+
+// csr_sweep_pre over the rows [row_begin, row_end) only (tiles of kTileRows
+// rows counted from row_begin): the red-black solver sweeps the rows of one
+// colour at a time.
+template <class VT, class Pre, class Body>
+__device__ inline void csr_sweep_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                      const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
+                                      int32_t *s_col, VT *s_val, Pre &&pre, Body &&body) {
+    using T = decltype(pre(int64_t(0)));
+    const int64_t rows = row_end - row_begin;
+    const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    auto tile_rows = [&](int64_t t) -> int { return (int)(rows - t * kTileRows < kTileRows ? rows - t * kTileRows : kTileRows); };
+    SlabPipe<VT> P;
+    T next{};
+    if (tr.first < tr.end) {
+        P.fetch_range(rp, col, val, row_begin + tr.first * kTileRows, tile_rows(tr.first));
+        if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
+    }
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t r0 = P.r0;
+        const int nr = P.nr, rs = P.rs, re = P.re;
+        const T cur = next;
+        P.commit(s_col, s_val);
+        __syncthreads();
+        if (t + tr.step < tr.end) {
+            P.fetch_range(rp, col, val, row_begin + (t + tr.step) * kTileRows, tile_rows(t + tr.step));
             if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
         }
         if ((int)threadIdx.x < nr) body(r0 + threadIdx.x, rs, re, cur);

@@ -1,0 +1,188 @@
+"""GPU solve with the DIC preconditioner in red-black order (opts.precond =
+CFD_PRECOND_DIC_RB) against the oracle's preconditioned CG, through the C ABI.
+
+The oracle runs PCG with M = (D + L) D^{-1} (D + U) in red-black elimination
+order on the full system; the library runs the same method in its Schur
+form (Jacobi-preconditioned CG on the black cells, red cells recovered), so
+in exact arithmetic the iterates match up to the first iteration the full
+form spends on the red block.  Bars: the true relative residual of the
+returned x, recomputed on the CPU, <= tol (+ its rounding bound); pressure
+error vs an oracle solution at 1e-13 <= 1e-9 (mean removed); float64
+iteration counts within 2 % + 2 of the oracle's PCG iterations.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2504_03697_amd as m
+    m.load()
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float64)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def true_relres(A, b, x):
+    return np.linalg.norm(b - oracle.spmv(A, x)) / np.linalg.norm(b)
+
+
+def relres_rounding(A, b, x):
+    g7 = 8 * 2.0**-53 / (1 - 8 * 2.0**-53)
+    absA = oracle.Csr(A.row_ptr, A.col, np.abs(A.val), A.dims, A.pin)
+    return g7 * np.linalg.norm(np.abs(b) + oracle.spmv(absA, np.abs(x))) / np.linalg.norm(b)
+
+
+def mean_removed_err(x, ref):
+    a, r = x - x.mean(), ref - ref.mean()
+    return np.linalg.norm(a - r) / np.linalg.norm(r)
+
+
+def make_rhs(dims, kind, seed):
+    b = synth.uniform_rhs(dims, seed) if kind == "uniform" else synth.smoothed_rhs(dims[0], seed)
+    return oracle.rhs_prepare(b, 0)
+
+
+def consistent_rhs(A_pin, b):
+    """Right-hand side of the projected formulation: c_i = b_i - b_pin for the
+    pin's neighbours, c_pin = -(sum of the others)."""
+    c = b.copy()
+    pin = A_pin.pin
+    nbrs = [A_pin.col[e] for e in range(A_pin.row_ptr[pin], A_pin.row_ptr[pin + 1]) if A_pin.col[e] != pin]
+    if not nbrs:  # the pin row is e_pin: find the neighbours from the Neumann matrix
+        An = oracle.assemble(A_pin.dims, -1)
+        nbrs = [An.col[e] for e in range(An.row_ptr[pin], An.row_ptr[pin + 1]) if An.col[e] != pin]
+    for j in nbrs:
+        c[j] = b[j] - b[pin]
+    c[pin] = 0.0
+    c[pin] = -c.sum()
+    return c
+
+
+CASES = [
+    ((16, 16, 16), "uniform", 0),
+    ((17, 17, 17), "smoothed", 1),
+    ((24, 13, 31), "uniform", 3),
+    ((33, 9, 21), "uniform", 4),
+    ((40, 40, 40), "smoothed", 9),
+]
+
+
+@pytest.mark.parametrize("dims,kind,seed", CASES)
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formulation", ["pinned", "projected"])
+def test_dic_solve_parity(lib, dims, kind, seed, precision, formulation):
+    tol = 1e-10
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, kind, seed)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(dims, 0)
+    print(f"dic parity {dims} {kind} seed {seed} {precision} {formulation}", flush=True)
+    x, info = lib.solve(A, dev(b), tol=tol, precision=precision, formulation=formulation, precond="dic")
+    x = host(x)
+    assert info["status"] == 0 and info["rel_residual"] <= tol
+    assert x[0] == 0.0
+    rr = true_relres(ref, b, x)
+    assert rr <= tol + relres_rounding(ref, b, x)
+    assert abs(rr - info["rel_residual"]) <= 0.05 * tol + relres_rounding(ref, b, x)
+    assert mean_removed_err(x, truth) <= 1e-9
+    if precision == "fp64":
+        if formulation == "pinned":
+            _, it, _, st = oracle.pcg(ref, b, tol=tol, precond="dic", redblack=True)
+        else:
+            An = oracle.assemble(dims, -1)
+            _, it, _, st = oracle.pcg(An, consistent_rhs(ref, b), tol=tol, precond="dic", redblack=True)
+        assert st == oracle.OK
+        assert abs(info["iters"] - it) <= 2 + 0.02 * it, (info["iters"], it)
+        # and it needs about half the iterations of plain CG
+        _, it_cg, _, _ = oracle.cg(ref, b, tol=tol)
+        if formulation == "pinned" and min(dims) >= 16:
+            assert info["iters"] <= 0.65 * it_cg
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 2, 3), (3, 1, 1)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_dic_tiny_grids(lib, dims, precision):
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, "uniform", 5)
+    A = lib.assemble(dims, 0)
+    for formulation in ("pinned", "projected"):
+        x, info = lib.solve(A, dev(b), tol=1e-12, precision=precision, formulation=formulation, precond="dic")
+        x = host(x)
+        assert info["status"] == 0
+        if np.any(b):
+            xd = np.linalg.solve(ref.dense(), b)
+            assert np.abs(x - xd).max() <= 1e-9 * max(np.abs(xd).max(), 1.0)
+        else:
+            assert not np.any(x)
+
+
+def test_dic_zero_rhs_and_guess(lib):
+    dims = (12, 10, 8)
+    ref = oracle.assemble(dims, 0)
+    A = lib.assemble(dims, 0)
+    x, info = lib.solve(A, dev(np.zeros(ref.n)), precond="dic", precision="mixed")
+    assert info["status"] == 0 and info["iters"] == 0 and not np.any(host(x))
+    b = make_rhs(dims, "uniform", 2)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    x0 = truth + 1e-4 * np.random.default_rng(0).standard_normal(ref.n)
+    x0[0] = 0.0
+    _, i0 = lib.solve(A, dev(b), precond="dic")
+    x, i1 = lib.solve(A, dev(b), x0=dev(x0), precond="dic")
+    assert i1["status"] == 0 and i1["iters"] < i0["iters"]
+    assert i1["init_residual"] < 1e-2
+    assert mean_removed_err(host(x), truth) <= 1e-9
+
+
+def test_dic_warm_start_network(lib):
+    dims = (16, 16, 16)
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, "smoothed", 3)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    rng = np.random.default_rng(4)
+    net = lib.Net((0.05 * rng.standard_normal(lib.Net().count)).astype(np.float32))
+    A = lib.assemble(dims, 0)
+    for precision in ("fp64", "mixed"):
+        x, info = lib.solve(A, dev(b), net=net, precision=precision, formulation="projected", precond="dic")
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+        assert mean_removed_err(host(x), truth) <= 1e-9
+
+
+def test_dic_noconv_and_determinism(lib):
+    dims = (20, 20, 20)
+    b = make_rhs(dims, "uniform", 1)
+    A = lib.assemble(dims, 0)
+    _, info = lib.solve(A, dev(b), precond="dic", max_iters=5, raise_on_error=False)
+    assert info["status"] == -4 and info["iters"] <= 5 + 16  # CFD_ENOCONV
+    for precision in ("fp64", "mixed"):
+        x1, i1 = lib.solve(A, dev(b), precond="dic", precision=precision, formulation="projected")
+        x2, i2 = lib.solve(A, dev(b), precond="dic", precision=precision, formulation="projected")
+        assert np.array_equal(host(x1), host(x2)) and i1["iters"] == i2["iters"]
+
+
+def test_dic_step_matches_oracle(lib):
+    """Cavity 16^3, 10 steps, with the preconditioned solve inside cfd_step."""
+    n, nu, dt = 16, 0.01, 0.005
+    S = lib.State(n, nu=nu, lid_u=1.0)
+    R = oracle.State(n, nu=nu, lid=1.0)
+    for s in range(10):
+        info = lib.step(S, dt, tol=1e-10, precision="mixed", formulation="projected", precond="dic")
+        _, _, st = oracle.step(R, dt, tol=1e-10)
+        assert st == oracle.OK and info["status"] == 0
+    sc = max(np.abs(R.u).max(), np.abs(R.v).max(), np.abs(R.w).max())
+    for f, g in ((S.u, R.u), (S.v, R.v), (S.w, R.w)):
+        assert np.abs(host(f) - g).max() <= 1e-7 * sc
