@@ -86,6 +86,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dic", action="store_true", help="skip the DIC-preconditioned comparison solves")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2504_03697_amd", "weights", "warmstart.npy"))
     args = ap.parse_args()
@@ -117,10 +118,10 @@ def main():
     torch.cuda.synchronize()
     log(f"{len(rhs)} right-hand sides resident in HBM")
 
-    def run(b, precision, use_net, form="projected"):
+    def run(b, precision, use_net, form="projected", precond="none"):
         m.rhs_prepare(A, b)
         x, info = m.solve(A, b, tol=args.tol, precision=precision, net=net if use_net else None, timing=True,
-                          formulation=form)
+                          formulation=form, precond=precond)
         return x, info
 
     for i in range(args.warmup):
@@ -137,26 +138,38 @@ def main():
     log(f"mixed{'+learned' if net else ''}: {ms_per_step:.1f} ms/solve, iters "
         f"{[i['iters'] for i in infos]}, relres max {max(i['rel_residual'] for i in infos):.2e}")
 
-    def compare(precision, use_net, form):
+    def compare(precision, use_net, form, precond="none"):
         out = []
+        if precond != "none":  # the first preconditioned solve builds the red-black matrix: keep it untimed
+            run(rhs[0], precision, use_net, form, precond)
+            torch.cuda.synchronize()
         t2 = time.perf_counter()
         for i in range(args.warmup, len(rhs)):
-            _, info = run(rhs[i], precision, use_net, form)
+            _, info = run(rhs[i], precision, use_net, form, precond)
             out.append(info)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         d = {"ms_per_solve": round((t3 - t2) * 1e3 / args.steps, 3), "iters": [i["iters"] for i in out],
-             "rel_residual_max": max(i["rel_residual"] for i in out),
-             "a_kernel_ms": round(float(np.mean([i["spmv_ms"] for i in out if i["spmv_samples"]])), 5)}
-        log(f"{precision} {form}{' +net' if use_net else ''}: {d['ms_per_solve']:.1f} ms/solve iters {d['iters']}")
+             "rel_residual_max": max(i["rel_residual"] for i in out)}
+        key = "a_kernel_ms" if precond == "none" else "s_product_ms"  # S product: the red + the black sweep
+        d[key] = round(float(np.mean([i["spmv_ms"] for i in out if i["spmv_samples"]])), 5)
+        log(f"{precision} {form}{' +net' if use_net else ''}{' +' + precond if precond != 'none' else ''}: "
+            f"{d['ms_per_solve']:.1f} ms/solve iters {d['iters']}")
         return d
 
-    fp64 = fp64p = mixed_nonet = None
+    fp64 = fp64p = mixed_nonet = dic_mixed = dic_mixed_net = dic_fp64 = None
     if not args.no_fp64:
         fp64 = compare("fp64", False, "pinned")
         fp64p = compare("fp64", False, "projected")
         if net is not None:
             mixed_nonet = compare("mixed", False, "projected")
+    if not args.no_dic:
+        # the paper's DIC preconditioner in red-black order (same tolerance, same right-hand sides)
+        dic_mixed = compare("mixed", False, "projected", "dic")
+        if net is not None:
+            dic_mixed_net = compare("mixed", True, "projected", "dic")
+        if not args.no_fp64:
+            dic_fp64 = compare("fp64", False, "projected", "dic")
 
     # dominant kernel: the mixed-precision CG SpMV kernel, sampled live with
     # HIP events on the solve stream inside the timed region
@@ -225,6 +238,11 @@ def main():
         "fp64_plain_pinned": fp64,
         "fp64_projected": fp64p,
         "mixed_projected_no_net": mixed_nonet,
+        "dic_mixed_projected": dic_mixed,
+        "dic_mixed_projected_learned": dic_mixed_net,
+        "dic_fp64_projected": dic_fp64,
+        "speedup_dic_mixed_vs_fp64_plain": (round(fp64["ms_per_solve"] / dic_mixed["ms_per_solve"], 3)
+                                            if fp64 and dic_mixed else None),
         "speedup_vs_fp64_plain": round(fp64["ms_per_solve"] / ms_per_step, 3) if fp64 else None,
         "speedup_vs_fp64_projected": round(fp64p["ms_per_solve"] / ms_per_step, 3) if fp64p else None,
         "spmv_fp32_isolated": {"ms": round(spmv_ms, 5), "gbs": round(spmv_gbs, 1),

@@ -1000,25 +1000,23 @@ struct RbMatrix {
     double *bS = nullptr, *xb = nullptr, *r64 = nullptr;
     double *y64 = nullptr, *yb = nullptr;       // red length
     double *z64 = nullptr, *p64[2] = {nullptr, nullptr}, *q64 = nullptr;
-    float *z32 = nullptr, *p32[2] = {nullptr, nullptr}, *q32 = nullptr, *y32 = nullptr;  // y32: red length
+    float *z32 = nullptr, *q32 = nullptr, *y32 = nullptr;  // y32: red length
+    float *ring32 = nullptr;                    // mixed: kRing directions, nb_pad apart
+    int64_t nb_pad = 0;
     double *part = nullptr;                     // 7 * gmax partial sums
     struct RbState *S = nullptr, *host = nullptr;
 };
 
-// Control state of the preconditioned solve: the CG state plus what the
-// black sweep needs from the red one of the same iteration.
+// Control state of the preconditioned solve: the CG state (same fields and
+// meaning; kept in its own buffers).
 struct RbState {
     CgState cg;
-    double cf;      // direction coefficient of the iteration in progress
-    double inv_s;   // 1 / scale of a restart in progress (mixed)
-    int32_t imode;  // mode of the iteration in progress
-    int32_t pad_;
 };
 
 void rb_free(RbMatrix *m) {
     if (!m) return;
     void *pp[] = {m->perm, m->iperm, m->rp, m->col, m->v64, m->v32, m->d64, m->d32, m->bp, m->bS, m->xb,
-                  m->r64, m->y64, m->yb, m->z64, m->p64[0], m->p64[1], m->q64, m->z32, m->p32[0], m->p32[1],
+                  m->r64, m->y64, m->yb, m->z64, m->p64[0], m->p64[1], m->q64, m->z32, m->ring32,
                   m->q32, m->y32, m->part, m->S};
     for (void *p : pp) if (p) (void)hipFree(p);
     if (m->host) (void)hipHostFree(m->host);
@@ -1173,8 +1171,8 @@ static int rb_buffers(RbMatrix *M, bool mixed) {
     if (h == hipSuccess && !M->host) h = hipHostMalloc((void **)&M->host, sizeof(RbState) * 2, 0);
     if (mixed) {
         if (h == hipSuccess) h = alloc(&M->z32, nb);
-        if (h == hipSuccess) h = alloc(&M->p32[0], nb);
-        if (h == hipSuccess) h = alloc(&M->p32[1], nb);
+        M->nb_pad = (nb + 63) / 64 * 64;
+        if (h == hipSuccess) h = alloc(&M->ring32, kRing * M->nb_pad);
         if (h == hipSuccess) h = alloc(&M->q32, nb);
         if (h == hipSuccess) h = alloc(&M->y32, nr);
     } else {
@@ -1207,16 +1205,43 @@ struct RbArgs {
     const double *x0, *y;   // initial guess or warm-start prediction (NULL = none)
     double *bp, *bS, *xb, *r64, *y64, *yb;
     double *z64, *p64a, *p64b, *q64;
-    float *z32, *p32a, *p32b, *q32, *y32;
+    float *z32, *q32, *y32;
+    float *ring32;          // mixed: ring of kRing direction buffers, nb_pad apart
+    int64_t nb_pad;
     double *partA, *partB, *partB2, *partF, *partFp, *partFz, *partF2;
     const double *partG1, *partG2, *partS;
     RbState *S;
 };
 
+// Mixed path: direction buffer k of the ring.
+__device__ inline float *rb_ring(const RbArgs &a, int k) { return a.ring32 + (int64_t)k * a.nb_pad; }
+
+// Direction buffers: mixed, ring slots (the current one, the next one);
+// float64, the two buffers.
+template <bool MIXED>
+__device__ inline void *rb_dir(const RbArgs &a, int pcur, bool next) {
+    if (MIXED) return rb_ring(a, next ? (pcur + 1) % kRing : pcur);
+    return (next ? !pcur : pcur) ? a.p64b : a.p64a;
+}
+
 __device__ inline bool rb_is_pin_nb(const RbArgs &a, int64_t i) {
     for (int q = 0; q < a.nnb; ++q)
         if (i == a.nbr[q]) return true;
     return false;
+}
+
+// Off-diagonal part of a red-black row over the staged slab: the diagonal is
+// entry rs, the neighbours rs+1 .. re-1 (unrolled over the 6 possible ones so
+// their gathers issue together).
+template <class Acc, class VT, class G>
+__device__ inline Acc rb_offdiag(const int32_t *s_col, const VT *s_val, int rs, int re, G &&g) {
+    Acc acc = Acc(0);
+#pragma unroll
+    for (int k = 1; k < kMaxRowNnz; ++k) {
+        const int e = rs + k;
+        if (e < re) acc = fma(Acc(s_val[e]), g(s_col[e]), acc);
+    }
+    return acc;
 }
 
 // Right-hand side in red-black order (projected: the consistent c) and the
@@ -1262,8 +1287,7 @@ __global__ void __launch_bounds__(kBlock) rb_init_red(RbArgs a) {
     __shared__ __align__(16) double s_val[kSlabLds];
     auto none = [](int64_t) { return 0; };
     csr_sweep_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
-        double acc = 0.0;
-        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], a.xb[s_col[e] - a.nr], acc);
+        const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.xb[c - a.nr]; });
         const double bi = a.bp[p], di = s_val[rs];
         a.y64[p] = (bi - acc) / di;
         a.yb[p] = bi / di;
@@ -1292,11 +1316,8 @@ __global__ void __launch_bounds__(kBlock) rb_init_black(RbArgs a, int64_t t) {
     const int64_t pin_p = a.perm[a.pin];
     auto none = [](int64_t) { return 0; };
     csr_sweep_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
-        double sy = 0.0, syb = 0.0;
-        for (int e = rs + 1; e < re; ++e) {
-            sy = fma(s_val[e], a.y64[s_col[e]], sy);
-            syb = fma(s_val[e], a.yb[s_col[e]], syb);
-        }
+        const double sy = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.y64[c]; });
+        const double syb = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.yb[c]; });
         const int64_t k = p - a.nr;
         const double bi = a.bp[p];
         a.bS[k] = bi - syb;
@@ -1452,10 +1473,15 @@ struct RbDir {
     }
 };
 
-// Red sweep: y = D_r^{-1} B p (p formed on the fly at the black neighbours).
+// Red sweep: y = D_r^{-1} B p, with p = z + cf p_old formed on the fly at the
+// black neighbours.  Red row p also forms and stores the new direction of
+// black cell p (the two are neighbours in space: both sit near natural index
+// 2p), loading that cell's z and p_old a tile ahead; those loads bring in the
+// lines the row's own gathers need.  In a restart it stores the new z too.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
+    typedef typename std::conditional<MIXED, f32x2, f64x2>::type VT2;
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) VT s_val[kSlabLds];
     __shared__ double red[kBlock / 64];
@@ -1480,24 +1506,34 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
     if (lead()) {
         RbState ns = st;
         ns.cg = D.ns;
-        ns.cf = (double)cf;
-        ns.inv_s = D.inv_s;
-        ns.imode = st.cg.mode;
         *out = ns;
     }
-    const VT *pold = MIXED ? (const VT *)(st.cg.pcur ? a.p32b : a.p32a) : (const VT *)(st.cg.pcur ? a.p64b : a.p64a);
-    const RbDir<MIXED> dir{a, pold, cf, D.inv_s, normal, normal || st.cg.mode == MODE_REFRESH};
+    const VT *pold = (const VT *)rb_dir<MIXED>(a, st.cg.pcur, false);
+    VT *pnew = (VT *)rb_dir<MIXED>(a, st.cg.pcur, true);
+    VT *z = MIXED ? (VT *)a.z32 : (VT *)a.z64;
+    const RbDir<MIXED> dir{a, pold, cf, D.inv_s, normal, normal || (MIXED && st.cg.mode == MODE_REFRESH)};
     VT *y = MIXED ? (VT *)a.y32 : (VT *)a.y64;
     const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
-    auto none = [](int64_t) { return 0; };
-    csr_sweep_rows<VT>(a.rp, a.col, val, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
-        VT acc = 0;
-        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], dir.w(s_col[e] - a.nr), acc);
+    // black cell k = p: its z and p_old, a tile ahead
+    auto own = [&](int64_t k) -> VT2 {
+        VT2 o;
+        o.x = k < a.nb ? dir.z(k) : VT(0);
+        o.y = (k < a.nb && dir.use_p) ? pold[k] : VT(0);
+        return o;
+    };
+    csr_sweep_rows<VT>(a.rp, a.col, val, 0, a.nr, s_col, s_val, own, [&](int64_t p, int rs, int re, VT2 o) {
+        const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return dir.w(c - a.nr); });
         y[p] = acc / s_val[rs];
+        if (p < a.nb) {
+            const VT wk = dir.use_p ? (VT)fma(dir.cf, o.y, o.x) : o.x;
+            if (!normal) store_stream(z + p, o.x);
+            pnew[p] = wk;  // plain store: the black sweep reads it next
+        }
     });
 }
 
-// Black sweep: p = z + cf p_old, q = D_b p - B^T y; partial sums of p^T q.
+// Black sweep: q = D_b p - B^T y with the direction p stored by the red
+// sweep; partial sums of p^T q.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
@@ -1510,24 +1546,16 @@ __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
         if (lead()) *out = st;
         return;
     }
-    const bool normal = st.imode == MODE_NORMAL;
-    const VT *pold = MIXED ? (const VT *)(st.cg.pcur ? a.p32b : a.p32a) : (const VT *)(st.cg.pcur ? a.p64b : a.p64a);
-    VT *pnew = MIXED ? (VT *)(st.cg.pcur ? a.p32a : a.p32b) : (VT *)(st.cg.pcur ? a.p64a : a.p64b);
+    const VT *pnew = (const VT *)rb_dir<MIXED>(a, st.cg.pcur, true);
     VT *q = MIXED ? (VT *)a.q32 : (VT *)a.q64;
-    VT *z = MIXED ? (VT *)a.z32 : (VT *)a.z64;
     const VT *y = MIXED ? (const VT *)a.y32 : (const VT *)a.y64;
     const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
-    const RbDir<MIXED> dir{a, pold, (VT)st.cf, st.inv_s, normal, normal || st.imode == MODE_REFRESH};
     double pq = 0.0;
-    auto own = [&](int64_t p) { return dir.z(p - a.nr); };
-    csr_sweep_rows<VT>(a.rp, a.col, val, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT zk) {
+    auto own = [&](int64_t p) { return pnew[p - a.nr]; };
+    csr_sweep_rows<VT>(a.rp, a.col, val, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT wk) {
         const int64_t k = p - a.nr;
-        const VT wk = dir.use_p ? (VT)fma(dir.cf, pold[k], zk) : zk;
-        VT acc = 0;
-        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], y[s_col[e]], acc);
+        const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return y[c]; });
         const VT qk = fma(s_val[rs], wk, -acc);
-        if (!normal) z[k] = zk;
-        store_stream(pnew + k, wk);
         store_stream(q + k, qk);
         pq = fma((double)wk, (double)qk, pq);
     });
@@ -1537,13 +1565,15 @@ __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
         RbState ns = st;
         ns.cg.mode = MODE_NORMAL;
         ns.cg.iters = st.cg.iters + 1;
-        ns.cg.pcur = 1 - st.cg.pcur;
+        ns.cg.pcur = MIXED ? (st.cg.pcur + 1) % kRing : 1 - st.cg.pcur;
         *out = ns;
     }
 }
 
-// Vector kernel: alpha = rho / p^T q; z -= alpha D_S^{-1} q; x_b += s alpha p
-// (float64); partial sums of ||D_S z||^2 and z^T D_S z.
+// Vector kernel: alpha = rho / p^T q; z -= alpha D_S^{-1} q; partial sums of
+// ||D_S z||^2 and z^T D_S z.  x_b += s alpha p in float64: every iteration
+// (float64 path), or queued and applied kDefer at a time, oldest first
+// (mixed path, as in the unpreconditioned solver).
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
@@ -1565,22 +1595,75 @@ __global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
         }
         return;
     }
-    const VT *p = MIXED ? (const VT *)(st.cg.pcur ? a.p32b : a.p32a) : (const VT *)(st.cg.pcur ? a.p64b : a.p64a);
     const VT *q = MIXED ? (const VT *)a.q32 : (const VT *)a.q64;
     VT *z = MIXED ? (VT *)a.z32 : (VT *)a.z64;
     const VT *d = MIXED ? (const VT *)a.d32 : (const VT *)a.d64;
     const VT av = (VT)alpha;
     const double sa = st.cg.scale * alpha;
+    const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x, stride = (int64_t)gridDim.x * kBlock;
+    if (!MIXED) {
+        const double *p = (const double *)rb_dir<false>(a, st.cg.pcur, false);
+        for (int64_t k = first; k < a.nb; k += stride) store_stream(a.xb + k, fma(sa, p[k], a.xb[k]));
+    } else if (st.cg.npend == kDefer - 1) {
+        const float *pe[kDefer];
+        double se[kDefer];
+#pragma unroll
+        for (int e = 0; e < kDefer; ++e) {
+            pe[e] = rb_ring(a, (st.cg.pcur - (kDefer - 1 - e) + kRing) % kRing);
+            se[e] = e < kDefer - 1 ? st.cg.sa[e] : sa;
+        }
+        // four black cells per thread and step, then the scalar tail
+        const int64_t nv = a.nb / 4;
+        f64x2 *x2 = reinterpret_cast<f64x2 *>(a.xb);
+        for (int64_t v = first; v < nv; v += stride) {
+            f64x2 xa = x2[2 * v], xc = x2[2 * v + 1];
+#pragma unroll
+            for (int e = 0; e < kDefer; ++e) {
+                const f32x4 pv = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(pe[e]) + v);
+                if (se[e] != 0.0) {
+                    xa.x = fma(se[e], (double)pv.x, xa.x);
+                    xa.y = fma(se[e], (double)pv.y, xa.y);
+                    xc.x = fma(se[e], (double)pv.z, xc.x);
+                    xc.y = fma(se[e], (double)pv.w, xc.y);
+                }
+            }
+            store_stream(x2 + 2 * v, xa);
+            store_stream(x2 + 2 * v + 1, xc);
+        }
+        for (int64_t k = nv * 4 + first; k < a.nb; k += stride) {
+            double xk = a.xb[k];
+#pragma unroll
+            for (int e = 0; e < kDefer; ++e)
+                if (se[e] != 0.0) xk = fma(se[e], (double)pe[e][k], xk);
+            store_stream(a.xb + k, xk);
+        }
+    }
     double rr = 0.0, rz = 0.0;
-    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < a.nb; k += (int64_t)gridDim.x * kBlock) {
-        const VT dk = d[k];
-        const VT zk = fma(-av, q[k] / dk, z[k]);
-        store_stream(z + k, zk);
-        store_stream(a.xb + k, fma(sa, (double)p[k], a.xb[k]));
+    auto upd = [&](VT dk, VT qk, VT zk0) -> VT {
+        const VT zk = fma(-av, qk / dk, zk0);
         const double rk = (double)dk * (double)zk;
         rr = fma(rk, rk, rr);
         rz = fma(rk, (double)zk, rz);
+        return zk;
+    };
+    int64_t tail = 0;
+    if (MIXED) {  // four black cells per thread and step (the buffers are 256-byte aligned)
+        const int64_t nv = a.nb / 4;
+        const f32x4 *d4 = reinterpret_cast<const f32x4 *>(a.d32);
+        const f32x4 *q4 = reinterpret_cast<const f32x4 *>(a.q32);
+        f32x4 *z4 = reinterpret_cast<f32x4 *>(a.z32);
+        for (int64_t v = first; v < nv; v += stride) {
+            const f32x4 dv = d4[v], qv = q4[v];
+            f32x4 zv = z4[v];
+            zv.x = (float)upd(dv.x, qv.x, zv.x);
+            zv.y = (float)upd(dv.y, qv.y, zv.y);
+            zv.z = (float)upd(dv.z, qv.z, zv.z);
+            zv.w = (float)upd(dv.w, qv.w, zv.w);
+            store_stream(z4 + v, zv);
+        }
+        tail = nv * 4;
     }
+    for (int64_t k = tail + first; k < a.nb; k += stride) store_stream(z + k, upd(d[k], q[k], z[k]));
     rr = block_sum(rr, red);
     rz = block_sum(rz, red);
     if (threadIdx.x == 0) {
@@ -1590,6 +1673,41 @@ __global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
     if (lead()) {
         RbState ns = st;
         ns.cg.alpha = alpha;
+        if (MIXED) {
+            if (st.cg.npend < kDefer - 1) {
+#pragma unroll
+                for (int e = 0; e < kDefer - 1; ++e)
+                    if (e == st.cg.npend) ns.cg.sa[e] = sa;
+                ns.cg.npend = st.cg.npend + 1;
+            } else {
+                ns.cg.npend = 0;  // applied above
+            }
+        }
+        *out = ns;
+    }
+}
+
+// Mixed path, before each refresh: when a refresh is pending, apply the
+// queued x updates (oldest first) and empty the queue, so the refresh and the
+// final x read x_b itself.
+__global__ void __launch_bounds__(kBlock) rb_apply(RbArgs a, int64_t t) {
+    const RbState st = a.S[t & 1];
+    RbState *out = &a.S[(t + 1) & 1];
+    if (st.cg.done || !st.cg.pending || st.cg.npend == 0) {
+        if (lead()) *out = st;
+        return;
+    }
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < a.nb; k += (int64_t)gridDim.x * kBlock) {
+        double xk = a.xb[k];
+        for (int e = 0; e < st.cg.npend; ++e) {
+            const int slot = (st.cg.pcur - (st.cg.npend - 1 - e) + kRing) % kRing;
+            if (st.cg.sa[e] != 0.0) xk = fma(st.cg.sa[e], (double)rb_ring(a, slot)[k], xk);
+        }
+        store_stream(a.xb + k, xk);
+    }
+    if (lead()) {
+        RbState ns = st;
+        ns.cg.npend = 0;
         *out = ns;
     }
 }
@@ -1604,8 +1722,7 @@ __global__ void __launch_bounds__(kBlock) rb_f1(RbArgs a, int64_t t) {
     if (st.cg.done || !st.cg.pending) return;
     auto none = [](int64_t) { return 0; };
     csr_sweep_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
-        double acc = 0.0;
-        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], a.xb[s_col[e] - a.nr], acc);
+        const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.xb[c - a.nr]; });
         a.y64[p] = acc / s_val[rs];
     });
 }
@@ -1626,8 +1743,7 @@ __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     double rr = 0.0, rp_ = 0.0, rz = 0.0;
     auto none = [](int64_t) { return 0; };
     csr_sweep_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
-        double acc = 0.0;
-        for (int e = rs + 1; e < re; ++e) acc = fma(s_val[e], a.y64[s_col[e]], acc);
+        const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.y64[c]; });
         const int64_t k = p - a.nr;
         const double ri = a.bS[k] - s_val[rs] * a.xb[k] + acc;
         a.r64[k] = ri;
@@ -1741,8 +1857,8 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     a.p64b = M->p64[1];
     a.q64 = M->q64;
     a.z32 = M->z32;
-    a.p32a = M->p32[0];
-    a.p32b = M->p32[1];
+    a.ring32 = M->ring32;
+    a.nb_pad = M->nb_pad;
     a.q32 = M->q32;
     a.y32 = M->y32;
     a.partA = M->part;
@@ -1818,6 +1934,10 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
                 ++t;
                 hipLaunchKernelGGL(rb_b<false>, dim3(a.Gv), dim3(kBlock), 0, s, a, t);
             }
+            ++t;
+        }
+        if (mixed) {
+            hipLaunchKernelGGL(rb_apply, dim3(a.Gv), dim3(kBlock), 0, s, a, t);
             ++t;
         }
         hipLaunchKernelGGL(rb_f1, dim3(a.G1), dim3(kBlock), 0, s, a, t);
