@@ -40,6 +40,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--formulation", default="pinned", choices=["pinned", "projected"])
     ap.add_argument("--net", default=None, help="warm-start weights (.npy)")
+    ap.add_argument("--precond", default="none", choices=["none", "dic"],
+                    help="dic: the DIC preconditioner in red-black order")
     ap.add_argument("--compare", action="store_true", help="also run plain FP64 pinned CG from the same state")
     ap.add_argument("--previous", action="store_true",
                     help="also run the same solver started from the previous step's pressure (no network)")
@@ -59,15 +61,17 @@ def main():
     S = m.State(n, nu=nu, lid_u=1.0)
     R = m.State(n, nu=nu, lid_u=1.0) if args.compare else None
     P = m.State(n, nu=nu, lid_u=1.0) if args.previous else None
-    log(f"{n}^3, Re={args.re:g}, dt={dt:g}, {args.steps} steps, {args.precision}/{args.formulation}"
+    log(f"{n}^3, Re={args.re:g}, dt={dt:g}, {args.steps} steps, {args.precision}/{args.formulation}/{args.precond}"
         f"{' + learned warm start' if net else ''}")
     rows = []
     for s in range(args.steps):
-        info = m.step(S, dt, tol=args.tol, precision=args.precision, net=net, formulation=args.formulation)
+        info = m.step(S, dt, tol=args.tol, precision=args.precision, net=net, formulation=args.formulation,
+                      precond=args.precond)
         row = {"step": s + 1, "iters": info["iters"], "seconds": round(info["seconds"], 4),
                "rel_residual": info["rel_residual"], "init_residual": info["init_residual"]}
         if P is not None:
-            ip = m.step(P, dt, tol=args.tol, precision=args.precision, formulation=args.formulation, guess="previous")
+            ip = m.step(P, dt, tol=args.tol, precision=args.precision, formulation=args.formulation, guess="previous",
+                        precond=args.precond)
             row.update({"prev_iters": ip["iters"], "prev_seconds": round(ip["seconds"], 4),
                         "prev_init_residual": ip["init_residual"]})
         if R is not None:
@@ -79,7 +83,7 @@ def main():
         rows.append(row)
         log(json.dumps(row))
     summ = {"grid": n, "re": args.re, "dt": dt, "steps": args.steps, "precision": args.precision,
-            "formulation": args.formulation, "learned": net is not None,
+            "formulation": args.formulation, "precond": args.precond, "learned": net is not None,
             "solve_seconds": round(sum(r["seconds"] for r in rows), 3),
             "iters_total": int(sum(r["iters"] for r in rows)),
             "max_rel_residual": max(r["rel_residual"] for r in rows)}
