@@ -279,6 +279,13 @@ def test_solve_256_mixed_full_size(lib):
     assert info64["status"] == 0
     assert true_relres(ref, b, x64) <= 1e-10 + relres_rounding(ref, b, x64)
     assert mean_removed_err(x64, truth) <= 1e-9
+    # the DIC-preconditioned solve (red-black order) at the same size
+    for precision in ("mixed", "fp64"):
+        xd, infod = lib.solve(A, bd, tol=1e-10, precision=precision, formulation="projected", precond="dic")
+        xd = host(xd)
+        assert infod["status"] == 0 and infod["iters"] < 0.6 * info["iters"]
+        assert true_relres(ref, b, xd) <= 1e-10 + relres_rounding(ref, b, xd)
+        assert mean_removed_err(xd, truth) <= 1e-9
 
 
 def test_solve_384_combined_size(lib):
@@ -288,10 +295,11 @@ def test_solve_384_combined_size(lib):
     ref = oracle.assemble(n, 0)
     b = make_rhs((n, n, n), "smoothed", 7)
     A = lib.assemble(n, 0)
-    x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation="projected")
-    x = host(x)
-    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
-    assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
+    for pc in ("none", "dic"):
+        x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation="projected", precond=pc)
+        x = host(x)
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+        assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
 
 
 def test_solve_edge_cases(lib):
