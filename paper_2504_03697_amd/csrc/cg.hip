@@ -1195,7 +1195,8 @@ struct RbArgs {
     const int32_t *perm, *iperm;
     double tol, ru_delta;
     int32_t max_iters;
-    int32_t G1, G2, Gv;     // red sweeps, black sweeps, black vector kernels
+    int32_t G1, G2, Gv;     // red and black sweeps of the iteration, black vector kernels
+    int32_t Gf1, Gf2;       // red and black sweeps of the initial residual and the refresh
     int32_t Gw, Gs;         // partial counts of the warm-start and right-hand-side sums
     int64_t pin;
     int32_t proj, nnb;
@@ -1381,9 +1382,9 @@ __device__ inline Decision rb_decide(const RbArgs &a, const CgState &st, double 
             ns.rmax = std::max(st.rmax, nr);
         }
     } else {
-        const double rr = reduce_partials(a.partF, a.G2, red);
-        const double rrp = reduce_partials(a.partFp, a.G2, red);
-        const double rz = reduce_partials(a.partFz, a.G2, red);
+        const double rr = reduce_partials(a.partF, a.Gf2, red);
+        const double rrp = reduce_partials(a.partFp, a.Gf2, red);
+        const double rz = reduce_partials(a.partFz, a.Gf2, red);
         if (st.mode == MODE_INIT) ns.bnorm = sqrt(reduce_partials(a.partF2, a.Gv, red));
         const double tr = sqrt(rr), trp = sqrt(rrp);
         const double bn = ns.bnorm;
@@ -1478,7 +1479,10 @@ struct RbDir {
 // black cell p (the two are neighbours in space: both sit near natural index
 // 2p), loading that cell's z and p_old a tile ahead; those loads bring in the
 // lines the row's own gathers need.  In a restart it stores the new z too.
-template <bool MIXED>
+// GENERAL = false is the normal-mode-only instance, without the restart's
+// float64 gathers: only the first launch after a refresh kernel can see a
+// restart, so the host launches the general instance there.
+template <bool MIXED, bool GENERAL>
 __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
     typedef typename std::conditional<MIXED, f32x2, f64x2>::type VT2;
@@ -1491,9 +1495,18 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
         if (lead()) *out = st;
         return;
     }
+    if (!GENERAL && st.cg.mode != MODE_NORMAL) {  // launch order broken: end the solve
+        if (lead()) {
+            RbState ns = st;
+            ns.cg.done = 1;
+            ns.cg.status = CFD_EHIP;
+            *out = ns;
+        }
+        return;
+    }
     const Decision D = rb_decide<MIXED>(a, st.cg, red);
     if (D.stop) {
-        if (D.ns.done) rb_write_x(a, D.zero_x);
+        if (GENERAL && D.ns.done) rb_write_x(a, D.zero_x);
         if (lead()) {
             RbState ns = st;
             ns.cg = D.ns;
@@ -1501,7 +1514,7 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
         }
         return;
     }
-    const bool normal = st.cg.mode == MODE_NORMAL;
+    const bool normal = !GENERAL || st.cg.mode == MODE_NORMAL;
     const VT cf = (VT)(normal ? D.beta : (MIXED ? D.cref : 0.0));
     if (lead()) {
         RbState ns = st;
@@ -1768,6 +1781,11 @@ __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     }
 }
 
+// Workgroups per CU of the red sweep's normal instance: measured at 256^3,
+// more resident workgroups make it slower (185 us at 8 per CU against 145 us
+// at 7), the gathers of the black vectors thrashing the XCD's L2.
+constexpr int kRbRedPerCu = 7;
+
 // Host driver of the preconditioned solve (options already validated).
 static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts &opts,
                          double *x, cfd_solve_info *info, hipStream_t s) {
@@ -1829,12 +1847,17 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     a.tol = tol;
     a.ru_delta = delta;
     a.max_iters = max_iters;
-    static const int k1_per_cu[2] = {resident_per_cu(rb_k1<false>), resident_per_cu(rb_k1<true>)};
+    // the red sweep writes no partial sums, so its two instances get grids of their own
+    static const int k1g_per_cu[2] = {resident_per_cu(rb_k1<false, true>), resident_per_cu(rb_k1<true, true>)};
+    static const int k1_per_cu[2] = {resident_per_cu(rb_k1<false, false>), resident_per_cu(rb_k1<true, false>)};
     static const int k2_per_cu[2] = {resident_per_cu(rb_k2<false>), resident_per_cu(rb_k2<true>)};
     static const int f_per_cu = std::min(std::min(resident_per_cu(rb_f1), resident_per_cu(rb_f2)),
                                          std::min(resident_per_cu(rb_init_red), resident_per_cu(rb_init_black)));
-    a.G1 = grid_tiles(nr, std::min(k1_per_cu[mixed], f_per_cu));
-    a.G2 = grid_tiles(nb, std::min(k2_per_cu[mixed], f_per_cu));
+    a.G1 = grid_tiles(nr, std::min(k1_per_cu[mixed], kRbRedPerCu));
+    const int G1g = grid_tiles(nr, k1g_per_cu[mixed]);
+    a.G2 = grid_tiles(nb, k2_per_cu[mixed]);
+    a.Gf1 = grid_tiles(nr, f_per_cu);
+    a.Gf2 = grid_tiles(nb, f_per_cu);
     a.Gv = grid_vec(nb);
     a.Gw = g.Gf;
     a.Gs = g.Gb;
@@ -1884,9 +1907,9 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     }
     if (proj) hipLaunchKernelGGL(rhs_sum, dim3(g.Gb), dim3(kBlock), 0, s, g);
     hipLaunchKernelGGL(rb_rhs, dim3(a.Gv), dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(rb_init_red, dim3(a.G1), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(rb_init_red, dim3(a.Gf1), dim3(kBlock), 0, s, a);
     int64_t t = 0;
-    hipLaunchKernelGGL(rb_init_black, dim3(a.G2), dim3(kBlock), 0, s, a, t);
+    hipLaunchKernelGGL(rb_init_black, dim3(a.Gf2), dim3(kBlock), 0, s, a, t);
     ++t;
     CFD_HIP(hipGetLastError());
 
@@ -1910,10 +1933,12 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
             smp = smp || time_it;
             // one product with S: the red sweep and the black sweep
             if (mixed) {
-                if (time_it)
-                    hipExtLaunchKernelGGL(rb_k1<true>, dim3(a.G1), dim3(kBlock), 0, s, w->ta[c], nullptr, 0, a, t);
+                if (i == 0)
+                    hipLaunchKernelGGL((rb_k1<true, true>), dim3(G1g), dim3(kBlock), 0, s, a, t);
+                else if (time_it)
+                    hipExtLaunchKernelGGL((rb_k1<true, false>), dim3(a.G1), dim3(kBlock), 0, s, w->ta[c], nullptr, 0, a, t);
                 else
-                    hipLaunchKernelGGL(rb_k1<true>, dim3(a.G1), dim3(kBlock), 0, s, a, t);
+                    hipLaunchKernelGGL((rb_k1<true, false>), dim3(a.G1), dim3(kBlock), 0, s, a, t);
                 ++t;
                 if (time_it)
                     hipExtLaunchKernelGGL(rb_k2<true>, dim3(a.G2), dim3(kBlock), 0, s, nullptr, w->tb[c], 0, a, t);
@@ -1922,10 +1947,12 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
                 ++t;
                 hipLaunchKernelGGL(rb_b<true>, dim3(a.Gv), dim3(kBlock), 0, s, a, t);
             } else {
-                if (time_it)
-                    hipExtLaunchKernelGGL(rb_k1<false>, dim3(a.G1), dim3(kBlock), 0, s, w->ta[c], nullptr, 0, a, t);
+                if (i == 0)
+                    hipLaunchKernelGGL((rb_k1<false, true>), dim3(G1g), dim3(kBlock), 0, s, a, t);
+                else if (time_it)
+                    hipExtLaunchKernelGGL((rb_k1<false, false>), dim3(a.G1), dim3(kBlock), 0, s, w->ta[c], nullptr, 0, a, t);
                 else
-                    hipLaunchKernelGGL(rb_k1<false>, dim3(a.G1), dim3(kBlock), 0, s, a, t);
+                    hipLaunchKernelGGL((rb_k1<false, false>), dim3(a.G1), dim3(kBlock), 0, s, a, t);
                 ++t;
                 if (time_it)
                     hipExtLaunchKernelGGL(rb_k2<false>, dim3(a.G2), dim3(kBlock), 0, s, nullptr, w->tb[c], 0, a, t);
@@ -1940,9 +1967,9 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
             hipLaunchKernelGGL(rb_apply, dim3(a.Gv), dim3(kBlock), 0, s, a, t);
             ++t;
         }
-        hipLaunchKernelGGL(rb_f1, dim3(a.G1), dim3(kBlock), 0, s, a, t);
+        hipLaunchKernelGGL(rb_f1, dim3(a.Gf1), dim3(kBlock), 0, s, a, t);
         ++t;
-        hipLaunchKernelGGL(rb_f2, dim3(a.G2), dim3(kBlock), 0, s, a, t);
+        hipLaunchKernelGGL(rb_f2, dim3(a.Gf2), dim3(kBlock), 0, s, a, t);
         ++t;
         CFD_HIP(hipGetLastError());
         sampled.push_back(smp);
