@@ -186,3 +186,22 @@ def test_dic_step_matches_oracle(lib):
     sc = max(np.abs(R.u).max(), np.abs(R.v).max(), np.abs(R.w).max())
     for f, g in ((S.u, R.u), (S.v, R.v), (S.w, R.w)):
         assert np.abs(host(f) - g).max() <= 1e-7 * sc
+
+
+@pytest.mark.parametrize("pin", [1, 8 * 9 * 3 + 9 * 4 + 4, 8 * 9 * 3 + 9 * 4 + 5])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formulation", ["pinned", "projected"])
+def test_dic_pinned_cell_colours(lib, pin, precision, formulation):
+    """The pinned cell on a black cell (i+j+k odd) and in the interior (both
+    colours): the pinned row sits in the Schur block or is eliminated."""
+    dims = (9, 8, 7)
+    ref = oracle.assemble(dims, pin)
+    b = oracle.rhs_prepare(synth.uniform_rhs(dims, 11), pin)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(dims, pin)
+    x, info = lib.solve(A, dev(b), tol=1e-10, precision=precision, formulation=formulation, precond="dic")
+    x = host(x)
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+    assert x[pin] == 0.0
+    assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
+    assert mean_removed_err(x, truth) <= 1e-9
