@@ -46,6 +46,22 @@ def a_kernel_bytes(n, nnz, mixed):
     return 4 * (n + 1) + nnz * (4 + w) + 4 * w * n + (0 if mixed else 16 * n)
 
 
+def s_product_bytes(n3):
+    """Algorithmic bytes of one product with the Schur complement on an N^3
+    grid in red-black order (projected formulation, float32 values and
+    vectors): the red sweep reads its rows' CSR (row pointers, columns, values
+    = diagonal + in-domain neighbours), z and p_old of the black cells and
+    writes y and the new direction; the black sweep reads its rows' CSR, the
+    direction and the gathered y, and writes q."""
+    n = n3 ** 3
+    nr = (n + 1) // 2
+    nb = n - nr
+    edges = 3 * n3 * n3 * (n3 - 1)
+    red = 4 * (nr + 1) + 8 * (nr + edges) + 8 * nb + 4 * nr + 4 * nb
+    black = 4 * (nb + 1) + 8 * (nb + edges) + 4 * nb + 4 * nr + 4 * nb
+    return red + black
+
+
 def kernel_source_sha():
     """Hash of the sources the CG kernels are built from."""
     h = hashlib.sha256()
@@ -153,6 +169,10 @@ def main():
              "rel_residual_max": max(i["rel_residual"] for i in out)}
         key = "a_kernel_ms" if precond == "none" else "s_product_ms"  # S product: the red + the black sweep
         d[key] = round(float(np.mean([i["spmv_ms"] for i in out if i["spmv_samples"]])), 5)
+        if precond != "none" and precision == "mixed" and form == "projected" and d[key] > 0:
+            sb = s_product_bytes(n)
+            d["s_product_bytes"] = sb
+            d["s_product_gbs"] = round(sb / (d[key] * 1e-3) / 1e9, 1)
         log(f"{precision} {form}{' +net' if use_net else ''}{' +' + precond if precond != 'none' else ''}: "
             f"{d['ms_per_solve']:.1f} ms/solve iters {d['iters']}")
         return d
