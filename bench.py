@@ -7,9 +7,11 @@ learned warm start (when trained weights are present), and the mixed
 FP32/FP64 reliable-update CG solve (projected formulation) to a relative
 residual of 1e-10.  The value is the mean time-to-tolerance per solve.  The
 same right-hand sides are then solved by plain FP64 CG on the pinned matrix
-(the plain method), by FP64 CG in the projected formulation, and by the mixed
-solver without the network, for the comparison factors; the CG SpMV kernel's
-launches inside the timed solves are timed with HIP events for the roofline.
+(the plain method), by FP64 CG in the projected formulation, by the mixed
+solver without the network, and with the paper's DIC preconditioner in
+red-black order (mixed, mixed + network, FP64), for the comparison factors;
+the CG SpMV kernel's launches inside the timed solves are timed with HIP
+events for the roofline.
 
 Prints ONE JSON line.  --gpus N > 1 is rejected: this build runs on one GPU.
 """
