@@ -13,7 +13,7 @@ red-black order (mixed, mixed + network, FP64), for the comparison factors;
 the CG SpMV kernel's launches inside the timed solves are timed with HIP
 events for the roofline.
 
-Prints ONE JSON line.  --gpus N > 1 is rejected: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 is rejected: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -109,7 +109,7 @@ def main():
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2504_03697_amd", "weights", "warmstart.npy"))
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on a single GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the solver runs on a single GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

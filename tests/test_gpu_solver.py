@@ -8,7 +8,7 @@ Tolerances (derived in DESIGN.md, "Parity bars"):
 * solve: true relative residual <= tol recomputed on the CPU (plus the
   rounding bound of that recomputation); pressure error vs an oracle
   solution at tol 1e-12 <= 1e-9 in relative L2 after removing the mean
-  (the spec bar); float64 iteration counts within 2 % + 2 of the
+  (the pressure-error bar); float64 iteration counts within 2 % + 2 of the
   oracle's (same algorithm, different summation order).
 """
 import numpy as np
