@@ -1098,8 +1098,6 @@ static int rb_build(cfd_csr_t A, bool proj, int gmax, hipStream_t s, RbMatrix **
                     iperm[p] = (int32_t)m;
                 }
     }
-    const int64_t pin_nb[6] = {pin >= 0 ? pin - nxny : -2, pin >= 0 ? pin - nx : -2, pin - 1, pin + 1,
-                               pin >= 0 ? pin + nx : -2, pin >= 0 ? pin + nxny : -2};
     int64_t e = 0;
     rp[0] = 0;
     for (int64_t p = 0; p < n; ++p) {
@@ -1114,7 +1112,6 @@ static int rb_build(cfd_csr_t A, bool proj, int gmax, hipStream_t s, RbMatrix **
             len = 1;
             for (int q = 0; q < 6; ++q) len += cand[q] >= 0 && cand[q] != pin;
         }
-        (void)pin_nb;
         e += len;
         if (e > (int64_t)INT32_MAX - kPad) return fail(CFD_EINVAL, "cfd_solve: red-black matrix exceeds int32 indexing");
         rp[p + 1] = (int32_t)e;
