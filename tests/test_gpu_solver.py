@@ -248,6 +248,33 @@ def test_solve_128_smoothed(lib, precision):
         assert mean_removed_err(x, truth) <= 1e-9
 
 
+def test_config_128_100_standalone_solves(lib):
+    """128^3 plain FP64 CG on 100 seeded Gaussian-smoothed right-hand sides
+    (zero mean, tol 1e-10): every returned x's true residual, recomputed by the
+    oracle's SpMV, meets the tolerance; two of the solves are compared with
+    the oracle's own solve (solution and iteration count)."""
+    n = 128
+    ref = oracle.assemble(n, 0)
+    A = lib.assemble(n, 0)
+    iters = []
+    for k in range(100):
+        # drawn by the seeded generator on the device, prepared by the oracle
+        raw = host(synth.smoothed_rhs_torch(n, 5000 + k)).reshape(-1)
+        b = oracle.rhs_prepare(raw, 0)
+        x, info = lib.solve(A, dev(b), tol=1e-10, precision="fp64")
+        x = host(x)
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-10, k
+        assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x), k
+        iters.append(info["iters"])
+        if k < 2:
+            truth, it, _, st = oracle.cg(ref, b, tol=1e-10)
+            assert st == oracle.OK
+            assert abs(info["iters"] - it) <= 2 + 0.02 * it
+            tight = oracle.cg(ref, b, tol=1e-12)[0]
+            assert mean_removed_err(x, tight) <= 1e-9
+    print(f"128^3, 100 solves: iterations {min(iters)}..{max(iters)}, mean {np.mean(iters):.1f}")
+
+
 _TRUTH = {}
 
 
