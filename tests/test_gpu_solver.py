@@ -315,6 +315,27 @@ def test_solve_256_mixed_full_size(lib):
         assert mean_removed_err(xd, truth) <= 1e-9
 
 
+def test_config_256_mixed_20_solves(lib):
+    """256^3 mixed precision (projected formulation) on 20 seeded smoothed
+    right-hand sides: every returned x's true FP64 residual, recomputed by the
+    oracle's SpMV, meets 1e-10 (the solution error against an oracle solve is
+    checked on one of them in test_solve_256_mixed_full_size)."""
+    n = 256
+    ref = oracle.assemble(n, 0)
+    A = lib.assemble(n, 0)
+    worst = 0.0
+    for k in range(20):
+        raw = host(synth.smoothed_rhs_torch(n, 7000 + k)).reshape(-1)
+        b = oracle.rhs_prepare(raw, 0)
+        x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation="projected")
+        x = host(x)
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-10, k
+        rr = true_relres(ref, b, x)
+        assert rr <= 1e-10 + relres_rounding(ref, b, x), k
+        worst = max(worst, rr)
+    print(f"256^3 mixed, 20 solves: worst true relative residual {worst:.3e}")
+
+
 def test_solve_384_combined_size(lib):
     """384^3 (56.6M unknowns, 395M nonzeros): mixed + projected converges and
     its true residual, recomputed by the oracle's SpMV, meets the tolerance."""
