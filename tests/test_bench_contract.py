@@ -21,3 +21,23 @@ def test_algorithmic_bytes():
     assert bench.a_kernel_bytes(n, nnz, False) == 4 * (n + 1) + 12 * nnz + 48 * n
     assert bench.spmv_bytes(n, nnz, 4) == 4 * (n + 1) + 8 * nnz + 8 * n
     assert len(bench.kernel_source_sha()) == 16
+
+
+def test_s_product_bytes_match_the_matrix():
+    """The byte model of the red-black S product counts the entries of the
+    Neumann matrix's red and black rows; check those counts on small grids
+    against the oracle's matrix split by colour."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import oracle
+    for N in (4, 6, 8):
+        A = oracle.assemble((N, N, N), -1)
+        n = N ** 3
+        idx = np.arange(n)
+        red = ((idx % N) + (idx // N) % N + idx // (N * N)) % 2 == 0
+        lens = np.diff(A.row_ptr)
+        nnz_r, nnz_b = int(lens[red].sum()), int(lens[~red].sum())
+        nr, nb = int(red.sum()), int((~red).sum())
+        want = (4 * (nr + 1) + 8 * nnz_r + 8 * nb + 4 * nr + 4 * nb) + (4 * (nb + 1) + 8 * nnz_b + 4 * nb + 4 * nr + 4 * nb)
+        assert bench.s_product_bytes(N) == want
