@@ -205,3 +205,33 @@ def test_dic_pinned_cell_colours(lib, pin, precision, formulation):
     assert x[pin] == 0.0
     assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
     assert mean_removed_err(x, truth) <= 1e-9
+
+
+def test_solves_on_a_side_stream(lib):
+    """All work goes on the caller's stream: solves (plain and preconditioned)
+    and a step issued on a non-default torch stream give the same answers as
+    on the default stream."""
+    dims = (20, 18, 16)
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, "uniform", 8)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(dims, 0)
+    side = torch.cuda.Stream()
+    for pc in ("none", "dic"):
+        x_def, i_def = lib.solve(A, dev(b), precision="mixed", formulation="projected", precond=pc)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            bs = dev(b)
+            x_side, i_side = lib.solve(A, bs, precision="mixed", formulation="projected", precond=pc)
+        side.synchronize()
+        assert i_side["status"] == 0 and i_side["iters"] == i_def["iters"]
+        assert np.array_equal(host(x_side), host(x_def))
+        assert mean_removed_err(host(x_side), truth) <= 1e-9
+    S1 = lib.State(12, nu=0.01, lid_u=1.0)
+    S2 = lib.State(12, nu=0.01, lid_u=1.0)
+    torch.cuda.synchronize()  # the states were initialised on the default stream
+    lib.step(S1, 0.005, precond="dic")
+    with torch.cuda.stream(side):
+        lib.step(S2, 0.005, precond="dic")
+    side.synchronize()
+    assert np.array_equal(host(S1.u), host(S2.u)) and np.array_equal(host(S1.p), host(S2.p))
