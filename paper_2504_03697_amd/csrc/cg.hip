@@ -1229,15 +1229,26 @@ __device__ inline bool rb_is_pin_nb(const RbArgs &a, int64_t i) {
 }
 
 // Off-diagonal part of a red-black row over the staged slab: the diagonal is
-// entry rs, the neighbours rs+1 .. re-1 (unrolled over the 6 possible ones so
-// their gathers issue together).
+// entry rs, the neighbours rs+1 .. re-1.  As in row_product, the gathers of
+// the 6 possible neighbours are issued together (slots past the row's end
+// gather the first neighbour again and are left out of the sum), so g is
+// only ever called with an off-diagonal column; a row without neighbours
+// (a pinned cell) gives 0.
 template <class Acc, class VT, class G>
 __device__ inline Acc rb_offdiag(const int32_t *s_col, const VT *s_val, int rs, int re, G &&g) {
     Acc acc = Acc(0);
+    if (re - rs < 2) return acc;
+    Acc v[kMaxRowNnz - 1], w[kMaxRowNnz - 1];
 #pragma unroll
     for (int k = 1; k < kMaxRowNnz; ++k) {
-        const int e = rs + k;
-        if (e < re) acc = fma(Acc(s_val[e]), g(s_col[e]), acc);
+        const int e = rs + k < re ? rs + k : rs + 1;
+        v[k - 1] = Acc(s_val[e]);
+        w[k - 1] = g(s_col[e]);
+    }
+#pragma unroll
+    for (int k = 1; k < kMaxRowNnz; ++k) {
+        const Acc f = fma(v[k - 1], w[k - 1], acc);
+        acc = rs + k < re ? f : acc;
     }
     return acc;
 }
@@ -1284,7 +1295,7 @@ __global__ void __launch_bounds__(kBlock) rb_init_red(RbArgs a) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) double s_val[kSlabLds];
     auto none = [](int64_t) { return 0; };
-    csr_sweep_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.xb[c - a.nr]; });
         const double bi = a.bp[p], di = s_val[rs];
         a.y64[p] = (bi - acc) / di;
@@ -1313,7 +1324,7 @@ __global__ void __launch_bounds__(kBlock) rb_init_black(RbArgs a, int64_t t) {
     double rr = 0.0, rp_ = 0.0, rz = 0.0;
     const int64_t pin_p = a.perm[a.pin];
     auto none = [](int64_t) { return 0; };
-    csr_sweep_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double sy = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.y64[c]; });
         const double syb = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.yb[c]; });
         const int64_t k = p - a.nr;
@@ -1531,7 +1542,7 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
         o.y = (k < a.nb && dir.use_p) ? pold[k] : VT(0);
         return o;
     };
-    csr_sweep_rows<VT>(a.rp, a.col, val, 0, a.nr, s_col, s_val, own, [&](int64_t p, int rs, int re, VT2 o) {
+    csr_stream_rows<VT>(a.rp, a.col, val, 0, a.nr, s_col, s_val, own, [&](int64_t p, int rs, int re, VT2 o) {
         const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return dir.w(c - a.nr); });
         y[p] = acc / s_val[rs];
         if (p < a.nb) {
@@ -1562,7 +1573,7 @@ __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
     const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
     double pq = 0.0;
     auto own = [&](int64_t p) { return pnew[p - a.nr]; };
-    csr_sweep_rows<VT>(a.rp, a.col, val, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT wk) {
+    csr_stream_rows<VT>(a.rp, a.col, val, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT wk) {
         const int64_t k = p - a.nr;
         const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return y[c]; });
         const VT qk = fma(s_val[rs], wk, -acc);
@@ -1731,7 +1742,7 @@ __global__ void __launch_bounds__(kBlock) rb_f1(RbArgs a, int64_t t) {
     if (lead()) *out = st;
     if (st.cg.done || !st.cg.pending) return;
     auto none = [](int64_t) { return 0; };
-    csr_sweep_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.xb[c - a.nr]; });
         a.y64[p] = acc / s_val[rs];
     });
@@ -1752,7 +1763,7 @@ __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     const int64_t pin_p = a.perm[a.pin];
     double rr = 0.0, rp_ = 0.0, rz = 0.0;
     auto none = [](int64_t) { return 0; };
-    csr_sweep_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.y64[c]; });
         const int64_t k = p - a.nr;
         const double ri = a.bS[k] - s_val[rs] * a.xb[k] + acc;

@@ -272,39 +272,6 @@ __device__ inline void csr_sweep_pre(const int32_t *__restrict__ rp, const int32
     }
 }
 
-// csr_sweep_pre over the rows [row_begin, row_end) only (tiles of kTileRows
-// rows counted from row_begin): the red-black solver sweeps the rows of one
-// colour at a time.
-template <class VT, class Pre, class Body>
-__device__ inline void csr_sweep_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                      const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
-                                      int32_t *s_col, VT *s_val, Pre &&pre, Body &&body) {
-    using T = decltype(pre(int64_t(0)));
-    const int64_t rows = row_end - row_begin;
-    const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
-    const TileRange tr = tile_range(ntiles);
-    auto tile_rows = [&](int64_t t) -> int { return (int)(rows - t * kTileRows < kTileRows ? rows - t * kTileRows : kTileRows); };
-    SlabPipe<VT> P;
-    T next{};
-    if (tr.first < tr.end) {
-        P.fetch_range(rp, col, val, row_begin + tr.first * kTileRows, tile_rows(tr.first));
-        if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
-    }
-    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
-        const int64_t r0 = P.r0;
-        const int nr = P.nr, rs = P.rs, re = P.re;
-        const T cur = next;
-        P.commit(s_col, s_val);
-        __syncthreads();
-        if (t + tr.step < tr.end) {
-            P.fetch_range(rp, col, val, row_begin + (t + tr.step) * kTileRows, tile_rows(t + tr.step));
-            if ((int)threadIdx.x < P.nr) next = pre(P.r0 + threadIdx.x);
-        }
-        if ((int)threadIdx.x < nr) body(r0 + threadIdx.x, rs, re, cur);
-        __syncthreads();
-    }
-}
-
 // Row product over the staged slab: sum_e val[e] * g(col[e]) in ascending
 // column order.  Rows of the 7-point matrix hold at most 7 entries.
 template <class Acc, class VT, class G>
@@ -314,6 +281,147 @@ __device__ inline Acc row_product(const int32_t *s_col, const VT *s_val, int rs,
     for (int k = 0; k < kMaxRowNnz; ++k) {
         const int e = rs + k;
         if (e < re) acc = fma(Acc(s_val[e]), g(s_col[e]), acc);
+    }
+    return acc;
+}
+
+// Slab loader of the streamed sweep below: the same tiles and slabs as
+// SlabPipe, with fewer waits.  A wave's memory counter drains in issue order,
+// so a wait for any load also waits for every older one.  fetch() therefore
+// takes the tile's entry bounds as arguments (loaded with the previous tile,
+// lanes 0 and 1 of bv) instead of loading them and waiting; every load it
+// issues is unconditional (indexes clamped into the tile); and the row
+// pointers it loads stay raw until the commit that consumes the slab.  So
+// nothing between a fetch and that commit waits for the slab, and the
+// row gathers of the current tile overlap it.  It costs registers: the
+// float32 SpMV and the red-black sweeps gain from it (3-4 % at 256^3), the
+// CG kernels with their extra per-row operands, and the float64 SpMV, do
+// not, and keep SlabPipe.
+template <class VT>
+struct SlabStream {
+    typedef typename std::conditional<sizeof(VT) == 8, f64x2, f32x4>::type VV;
+    static constexpr int kPerV = sizeof(VV) / sizeof(VT);  // values per vector load
+    static constexpr int kVecC = (kSlab + 4 * kBlock - 1) / (4 * kBlock);
+    static constexpr int kVecV = (kSlab + kPerV * kBlock - 1) / (kPerV * kBlock);
+    i32x4 rc[kVecC];
+    VV rv[kVecV];
+    int64_t r0 = 0;
+    int nr = 0, ea = 0, cnt = 0, e0 = 0;
+    int rsr = 0, rer = 0;  // row_ptr of this thread's row (clamped into the tile) and the next
+    int bv = 0;            // lane 0: row_ptr at the start of the tile after; lane 1: at its end
+
+    // Load the nr_ rows from r0_, whose entries are [b0, b1), and the entry
+    // bounds of the nq rows from q0 (the tile fetched next).  b1 > b0.
+    __device__ inline void fetch(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                 const VT *__restrict__ val, int64_t r0_, int nr_, int b0, int b1, int64_t q0,
+                                 int nq) {
+        const int tid = threadIdx.x;
+        r0 = r0_;
+        nr = nr_;
+        e0 = b0;
+        ea = b0 & ~3;
+        cnt = b1 - ea;
+        const int lastc = (cnt - 1) >> 2, lastv = (cnt - 1) / kPerV;
+        const i32x4 *c4 = reinterpret_cast<const i32x4 *>(col + ea);
+        const VV *v4 = reinterpret_cast<const VV *>(val + ea);
+#pragma unroll
+        for (int v = 0; v < kVecC; ++v) rc[v] = __builtin_nontemporal_load(c4 + min(tid + v * kBlock, lastc));
+#pragma unroll
+        for (int v = 0; v < kVecV; ++v) rv[v] = __builtin_nontemporal_load(v4 + min(tid + v * kBlock, lastv));
+        const int64_t rr = r0 + min(tid, nr - 1);
+        rsr = rp[rr];
+        rer = rp[rr + 1];
+        bv = rp[q0 + ((tid & 63) == 1 ? nq : 0)];
+    }
+
+    // Entry bounds of the tile after the fetched one (uniform).
+    __device__ inline void bounds(int &b0, int &b1) const {
+        b0 = __builtin_amdgcn_readfirstlane(bv);
+        b1 = __builtin_amdgcn_readlane(bv, 1);
+    }
+
+    __device__ inline void commit(int32_t *s_col, VT *s_val) const {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int v = 0; v < kVecC; ++v)
+            if ((tid + v * kBlock) * 4 < cnt) reinterpret_cast<i32x4 *>(s_col)[tid + v * kBlock] = rc[v];
+#pragma unroll
+        for (int v = 0; v < kVecV; ++v)
+            if ((tid + v * kBlock) * kPerV < cnt) reinterpret_cast<VV *>(s_val)[tid + v * kBlock] = rv[v];
+    }
+};
+
+// Sweep the rows [row_begin, row_end) in tiles of kTileRows rows counted from
+// row_begin, the tiles assigned to this workgroup by the XCD-aware schedule.
+// pre(i) loads what the body needs from row i's own vector entries; it runs
+// for the next tile while the current one computes (it must accept any row
+// of the range: rows past a tile's end are clamped to its last row).  Once a
+// tile's slab is in LDS, body(i, rs, re, v) runs for every row i of the tile
+// owned by this thread (one row per thread), with [rs, re) the row's entries
+// in s_col/s_val and v = pre(i).  The call is workgroup-uniform; every row
+// holds at least one entry.
+template <class VT, class Pre, class Body>
+__device__ inline void csr_stream_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                      const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
+                                      int32_t *s_col, VT *s_val, Pre &&pre, Body &&body) {
+    using T = decltype(pre(int64_t(0)));
+    const int64_t rows = row_end - row_begin;
+    const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
+    const TileRange tr = tile_range(ntiles);
+    if (tr.first >= tr.end) return;
+    auto tile_r0 = [&](int64_t t) -> int64_t { return row_begin + t * kTileRows; };
+    auto tile_nr = [&](int64_t t) -> int {
+        return (int)(rows - t * kTileRows < kTileRows ? rows - t * kTileRows : kTileRows);
+    };
+    const int tid = threadIdx.x;
+    SlabStream<VT> P;
+    {
+        const int64_t t = tr.first, tq = t + tr.step < tr.end ? t + tr.step : t;
+        const int64_t r0 = tile_r0(t);
+        const int nr = tile_nr(t);
+        P.fetch(rp, col, val, r0, nr, rp[r0], rp[r0 + nr], tile_r0(tq), tile_nr(tq));
+    }
+    T next = pre(P.r0 + min(tid, P.nr - 1));
+    for (int64_t t = tr.first; t < tr.end; t += tr.step) {
+        const int64_t r0 = P.r0;
+        const int nr = P.nr, e0 = P.e0;
+        const int rs = P.rsr - P.ea, re = P.rer - P.ea;
+        const T cur = next;
+        int b0, b1;
+        P.bounds(b0, b1);
+        P.commit(s_col, s_val);
+        __syncthreads();
+        // After the last tile the fetch re-reads the current tile's first
+        // vector, so every iteration issues the same loads.
+        const int64_t tn = t + tr.step;
+        const bool more = tn < tr.end;
+        const int64_t tq = tn + tr.step < tr.end ? tn + tr.step : tn;
+        P.fetch(rp, col, val, more ? tile_r0(tn) : r0, more ? tile_nr(tn) : nr, more ? b0 : e0,
+                more ? b1 : e0 + 1, more ? tile_r0(tq) : r0, more ? tile_nr(tq) : nr);
+        next = pre(P.r0 + min(tid, P.nr - 1));
+        if (tid < nr) body(r0 + tid, rs, re, cur);
+        __syncthreads();
+    }
+}
+
+// row_product with all gathers issued before the first multiply-add: the
+// slots past the row's end gather the row's first entry again and are left
+// out of the sum by a select, which adds the same terms in the same order as
+// row_product (bit-identical results).  The row holds at least one entry.
+template <class Acc, class VT, class G>
+__device__ inline Acc row_product_all(const int32_t *s_col, const VT *s_val, int rs, int re, G &&g) {
+    Acc v[kMaxRowNnz], w[kMaxRowNnz];
+#pragma unroll
+    for (int k = 0; k < kMaxRowNnz; ++k) {
+        const int e = rs + k < re ? rs + k : rs;
+        v[k] = Acc(s_val[e]);
+        w[k] = g(s_col[e]);
+    }
+    Acc acc = Acc(0);
+#pragma unroll
+    for (int k = 0; k < kMaxRowNnz; ++k) {
+        const Acc f = fma(v[k], w[k], acc);
+        acc = rs + k < re ? f : acc;
     }
     return acc;
 }

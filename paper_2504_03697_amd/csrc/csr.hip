@@ -260,9 +260,17 @@ __global__ void __launch_bounds__(kBlock) spmv_kernel(const int32_t *__restrict_
                                                       const VT *__restrict__ x, VT *__restrict__ y) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) VT s_val[kSlabLds];
-    csr_sweep<VT>(rp, col, val, n, s_col, s_val, [&](int64_t i, int rs, int re) {
-        store_stream(y + i, row_product<VT>(s_col, s_val, rs, re, [&](int j) { return x[j]; }));
-    });
+    auto xg = [&](int j) { return x[j]; };
+    if constexpr (sizeof(VT) == 4) {
+        csr_stream_rows<VT>(rp, col, val, 0, n, s_col, s_val, [](int64_t) { return 0; },
+                            [&](int64_t i, int rs, int re, int) {
+                                store_stream(y + i, row_product_all<VT>(s_col, s_val, rs, re, xg));
+                            });
+    } else {
+        csr_sweep<VT>(rp, col, val, n, s_col, s_val, [&](int64_t i, int rs, int re) {
+            store_stream(y + i, row_product<VT>(s_col, s_val, rs, re, xg));
+        });
+    }
 }
 
 // Partial sums of b for the mean.
