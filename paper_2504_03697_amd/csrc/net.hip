@@ -14,7 +14,7 @@
 // steps for 16 input channels, 1 step for the single-channel input layer),
 // A = the layer's weights (pre-packed per lane), and B = the input values at
 // the clamped neighbour of each voxel (a 16-byte read per lane from the
-// workgroup's input brick staged in LDS).  The 16x16 accumulator holds four
+// input planes the workgroup stages in LDS as it marches along z).  The 16x16 accumulator holds four
 // consecutive channels of one voxel per lane, so the output is written as one
 // 8-byte (bf16) or 16-byte (float) store.
 //
@@ -138,98 +138,152 @@ __global__ void __launch_bounds__(kBlock) conv_mfma(Geo g, const uint16_t *__res
     }
 }
 
-// Forward convolution with the input brick staged in LDS.  A workgroup
-// computes an output brick of kBX x kBY x kBZ voxels (16 MFMA tiles of 16
-// voxels along x); its input halo, (kBX+2) x (kBY+2) x (kBZ+2) voxels with
-// replicate padding applied while loading, is read from HBM once into LDS,
-// and every tap's B operand is then a 16-byte LDS read instead of a global
-// gather.
-constexpr int kBX = 16, kBY = 8, kBZ = 2;
-constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
-constexpr int kHalo = kHX * kHY * kHZ;
+// Forward convolution marching along z.  A work item is a column of
+// kTX x kTY output voxels (one 16-voxel MFMA tile per y row, 4 rows per
+// wave) over zc consecutive z planes.  The input planes z-1, z and z+1 of the
+// column's halo ((kTX+2) x (kTY+2) voxels, replicate padding applied while
+// loading) sit in a 3-slot LDS ring; plane z+2 is loaded into registers while
+// plane z computes and is committed into the slot of plane z-1 afterwards.
+// Each input plane is thus read once per column, plus the column's halo ring
+// (18 x 18 / 16 x 16) and two boundary planes per z range, and every tap's B
+// operand is a 16-byte LDS read, issued four steps ahead of its matrix
+// instruction.  At 16 input channels those reads (1 KB per 16x16x32 step)
+// bound the kernel: LDS delivers 128 bytes per clock per CU, half of what the
+// matrix cores would consume at their full rate.  Work items run in XCD-contiguous
+// ranges so neighbouring columns share their halo in one L2.
+constexpr int kTX = 16, kTY = 16;
+constexpr int kPX = kTX + 2, kPY = kTY + 2, kPlane = kPX * kPY;
+
+template <int CIN>
+struct PlaneRegs {
+    // CIN = 16: a plane is kPlane * 2 16-byte chunks; CIN = 1: kPlane values
+    static constexpr int kN = CIN == 16 ? (kPlane * 2 + kBlock - 1) / kBlock : (kPlane + kBlock - 1) / kBlock;
+    typedef typename std::conditional<CIN == 16, u16x8, uint16_t>::type T;
+    T v[kN];
+};
 
 template <int CIN, int COUT, bool OUT_BF16>
-__global__ void __launch_bounds__(kBlock) conv_fwd_lds(Geo g, const uint16_t *__restrict__ in,
-                                                       const u16x8 *__restrict__ frag, void *__restrict__ out,
-                                                       int relu) {
+__global__ void __launch_bounds__(kBlock) conv_fwd_z(Geo g, int zc, const uint16_t *__restrict__ in,
+                                                     const u16x8 *__restrict__ frag, void *__restrict__ out,
+                                                     int relu) {
     constexpr int STEPS = CIN == 16 ? 14 : 1;
-    __shared__ __align__(16) uint16_t s_in[kHalo * CIN];
+    __shared__ __align__(16) uint16_t s_in[3 * kPlane * CIN];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nl = lane & 15, grp = lane >> 4;
     bf16x8 A[STEPS];
 #pragma unroll
     for (int s = 0; s < STEPS; ++s) A[s] = __builtin_bit_cast(bf16x8, frag[s * 64 + lane]);
-    const int nbx = (g.nx + kBX - 1) / kBX, nby = (g.ny + kBY - 1) / kBY, nbz = (g.nz + kBZ - 1) / kBZ;
-    const int64_t nbricks = (int64_t)nbx * nby * nbz;
-    for (int64_t br = blockIdx.x; br < nbricks; br += gridDim.x) {
-        const int bx0 = (int)(br % nbx) * kBX, by0 = (int)((br / nbx) % nby) * kBY,
-                  bz0 = (int)(br / ((int64_t)nbx * nby)) * kBZ;
-        // stage the halo (clamped coordinates = replicate padding)
-        if constexpr (CIN == 16) {
-            for (int c = threadIdx.x; c < kHalo * 2; c += kBlock) {
-                const int h = c >> 1, half = c & 1;
-                const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-                const int64_t src = (int64_t)clampi(bx0 + hx - 1, 0, g.nx - 1) +
-                                    (int64_t)g.nx * ((int64_t)clampi(by0 + hy - 1, 0, g.ny - 1) +
-                                                     (int64_t)g.ny * clampi(bz0 + hz - 1, 0, g.nz - 1));
-                reinterpret_cast<u16x8 *>(s_in)[c] = *reinterpret_cast<const u16x8 *>(in + src * 16 + 8 * half);
-            }
-        } else {
-            for (int h = threadIdx.x; h < kHalo; h += kBlock) {
-                const int hx = h % kHX, hy = (h / kHX) % kHY, hz = h / (kHX * kHY);
-                const int64_t src = (int64_t)clampi(bx0 + hx - 1, 0, g.nx - 1) +
-                                    (int64_t)g.nx * ((int64_t)clampi(by0 + hy - 1, 0, g.ny - 1) +
-                                                     (int64_t)g.ny * clampi(bz0 + hz - 1, 0, g.nz - 1));
-                s_in[h] = in[src];
-            }
-        }
-        __syncthreads();
-        // 16 tiles (one x-row of 16 voxels each), 4 per wave
-        for (int ti = wave; ti < kBY * kBZ; ti += kBlock / 64) {
-            const int ty = ti % kBY, tz = ti / kBY;
-            const int x = bx0 + nl, y = by0 + ty, z = bz0 + tz;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int ntx = (g.nx + kTX - 1) / kTX, nty = (g.ny + kTY - 1) / kTY, nzc = (g.nz + zc - 1) / zc;
+    const TileRange tr = tile_range((int64_t)ntx * nty * nzc);
+    for (int64_t item = tr.first; item < tr.end; item += tr.step) {
+        const int x0 = (int)(item % ntx) * kTX, y0 = (int)((item / ntx) % nty) * kTY;
+        const int z0 = (int)(item / ((int64_t)ntx * nty)) * zc;
+        const int z1 = min(z0 + zc, g.nz);
+        // halo plane p (clamped into the grid) into registers / into its slot
+        auto load = [&](int p, PlaneRegs<CIN> &R) {
+            const int64_t zoff = (int64_t)g.nx * g.ny * clampi(p, 0, g.nz - 1);
 #pragma unroll
-            for (int s = 0; s < STEPS; ++s) {
-                u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int q = 0; q < PlaneRegs<CIN>::kN; ++q) {
+                const int c = threadIdx.x + q * kBlock;
+                const int h = CIN == 16 ? (c >> 1) : c;
+                const int hh = min(h, kPlane - 1);
+                const int hx = hh % kPX, hy = hh / kPX;
+                const int64_t src = zoff + clampi(x0 + hx - 1, 0, g.nx - 1) +
+                                    (int64_t)g.nx * clampi(y0 + hy - 1, 0, g.ny - 1);
+                if constexpr (CIN == 16) R.v[q] = *reinterpret_cast<const u16x8 *>(in + src * 16 + 8 * (c & 1));
+                else R.v[q] = in[src];
+            }
+        };
+        auto commit = [&](int p, const PlaneRegs<CIN> &R) {
+            const int slot = (p + 3) % 3;
+#pragma unroll
+            for (int q = 0; q < PlaneRegs<CIN>::kN; ++q) {
+                const int c = threadIdx.x + q * kBlock;
                 if constexpr (CIN == 16) {
-                    const int t = 2 * s + (grp >> 1);
-                    if (t < 27) {
-                        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-                        const int h = (nl + 1 + dx) + kHX * ((ty + 1 + dy) + kHY * (tz + 1 + dz));
-                        b = reinterpret_cast<const u16x8 *>(s_in)[2 * h + (grp & 1)];
-                    }
+                    if (c < kPlane * 2) reinterpret_cast<u16x8 *>(s_in)[slot * kPlane * 2 + c] = R.v[q];
                 } else {
+                    if (c < kPlane) s_in[slot * kPlane + c] = R.v[q];
+                }
+            }
+        };
+        PlaneRegs<CIN> R;
+        for (int p = z0 - 1; p <= z0 + 1; ++p) {
+            load(p, R);
+            commit(p, R);
+        }
+        load(z0 + 2, R);
+        __syncthreads();
+        for (int z = z0; z < z1; ++z) {
+            // 16 tiles (rows of 16 voxels along x), 4 per wave
+            for (int ty = wave; ty < kTY; ty += kBlock / 64) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                u16x8 bb[STEPS];
+                if constexpr (CIN == 16) {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const int t = 8 * grp + e;
-                        if (t < 27) {
-                            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-                            b[e] = s_in[(nl + 1 + dx) + kHX * ((ty + 1 + dy) + kHY * (tz + 1 + dz))];
+                    for (int s = 0; s < STEPS; ++s) {
+                        // tap 27 (the padding half of the last step) reads tap 26's
+                        // operand; its weights are zero
+                        const int t = min(2 * s + (grp >> 1), 26);
+                        const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                        const int slot = (z + dz + 3) % 3;
+                        const int h = (nl + 1 + dx) + kPX * (ty + 1 + dy);
+                        bb[s] = reinterpret_cast<const u16x8 *>(s_in)[(slot * kPlane + h) * 2 + (grp & 1)];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < STEPS; ++s) {
+                    u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if constexpr (CIN == 16) {
+                        b = bb[s];
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int t = 8 * grp + e;
+                            if (t < 27) {
+                                const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                                const int slot = (z + dz + 3) % 3;
+                                b[e] = s_in[slot * kPlane + (nl + 1 + dx) + kPX * (ty + 1 + dy)];
+                            }
                         }
                     }
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s], __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
                 }
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[s], __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
-            }
-            if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
-            const int64_t o = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
-            if (relu) {
+                if constexpr (CIN == 16) {
+                    // keep 4 operand reads in flight ahead of the matrix ops
+                    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc[q] = acc[q] > 0.f ? acc[q] : 0.f;
-            }
-            if constexpr (COUT == 16) {
-                if constexpr (OUT_BF16) {
-                    u16x4 v = {f2bf(acc[0]), f2bf(acc[1]), f2bf(acc[2]), f2bf(acc[3])};
-                    *reinterpret_cast<u16x4 *>((uint16_t *)out + o * 16 + 4 * grp) = v;
-                } else {
-                    *reinterpret_cast<f32x4 *>((float *)out + o * 16 + 4 * grp) = acc;
+                    for (int s = 0; s < STEPS - 4; ++s) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
+                    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
                 }
-            } else if (grp == 0) {
-                if constexpr (OUT_BF16) ((uint16_t *)out)[o] = f2bf(acc[0]);
-                else ((float *)out)[o] = acc[0];
+                const int x = x0 + nl, y = y0 + ty;
+                if (x >= g.nx || y >= g.ny) continue;
+                const int64_t o = (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
+                if (relu) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] = acc[q] > 0.f ? acc[q] : 0.f;
+                }
+                if constexpr (COUT == 16) {
+                    if constexpr (OUT_BF16) {
+                        u16x4 v = {f2bf(acc[0]), f2bf(acc[1]), f2bf(acc[2]), f2bf(acc[3])};
+                        *reinterpret_cast<u16x4 *>((uint16_t *)out + o * 16 + 4 * grp) = v;
+                    } else {
+                        *reinterpret_cast<f32x4 *>((float *)out + o * 16 + 4 * grp) = acc;
+                    }
+                } else if (grp == 0) {
+                    if constexpr (OUT_BF16) ((uint16_t *)out)[o] = f2bf(acc[0]);
+                    else ((float *)out)[o] = acc[0];
+                }
             }
+            __syncthreads();  // every wave is done with the slot of plane z-1
+            if (z + 1 < z1) {
+                commit(z + 2, R);
+                load(z + 3, R);
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -446,11 +500,25 @@ static int grid_waves(int64_t work_items_per_wave_units) {
 template <int CIN, int COUT, int MODE, bool OUT_BF16>
 static void launch_conv(const Geo &g, const uint16_t *in, const uint16_t *frag, void *out, int relu, hipStream_t s) {
     if constexpr (MODE == FWD) {
-        const int64_t nb = (int64_t)((g.nx + kBX - 1) / kBX) * ((g.ny + kBY - 1) / kBY) * ((g.nz + kBZ - 1) / kBZ);
+        // z ranges sized so the work items about fill the resident workgroups
+        static const int per_cu = [] {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, conv_fwd_z<CIN, COUT, OUT_BF16>, kBlock, 0) !=
+                    hipSuccess ||
+                nb < 1)
+                nb = 1;
+            return nb;
+        }();
         Device d;
         if (device_info(&d) != CFD_OK) d.cus = 256;
-        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(nb, (int64_t)d.cus * 6));
-        hipLaunchKernelGGL((conv_fwd_lds<CIN, COUT, OUT_BF16>), dim3(blocks), dim3(kBlock), 0, s, g, in,
+        const int64_t resident = (int64_t)per_cu * d.cus;
+        const int64_t ncol = (int64_t)((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY);
+        const int64_t want = std::max<int64_t>(1, std::min<int64_t>(g.nz, (resident + ncol - 1) / ncol));
+        const int zc = (int)((g.nz + want - 1) / want);
+        const int64_t items = ncol * ((g.nz + zc - 1) / zc);
+        int blocks = (int)std::min<int64_t>(items, resident);
+        if (blocks > kXcd) blocks -= blocks % kXcd;
+        hipLaunchKernelGGL((conv_fwd_z<CIN, COUT, OUT_BF16>), dim3(blocks), dim3(kBlock), 0, s, g, zc, in,
                            (const u16x8 *)frag, out, relu);
         return;
     }
