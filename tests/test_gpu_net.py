@@ -67,6 +67,21 @@ def test_conv_forward(lib, cin, cout, dims):
 
 
 @pytest.mark.parametrize("cin,cout", SHAPES)
+@pytest.mark.parametrize("dims", [(130, 66, 40), (33, 47, 5)])
+def test_conv_forward_many_columns(lib, cin, cout, dims):
+    """Grids of several 16 x 16 columns with ragged edges, marched in z ranges
+    of several planes (130 x 66 x 40: 9 x 5 columns, z ranges of 3 planes and a
+    last range of 1 on a full-size device)."""
+    n = int(np.prod(dims))
+    x = synth.bf16_values(n * cin, 3)
+    w = synth.bf16_values(27 * cin * cout, 4, scale=0.3)
+    ref = oracle.conv3d_fwd(dims, x, w, cin, cout)
+    absref = oracle.conv3d_fwd(dims, np.abs(x), np.abs(w), cin, cout)
+    y = host(lib.conv3d_forward(dims, cin, cout, bits(x), bits(w), relu=True))
+    assert np.all(np.abs(y - np.maximum(ref, 0)) <= gamma(27 * cin) * absref * 1.01 + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout", SHAPES)
 @pytest.mark.parametrize("dims", GRIDS)
 def test_conv_backward_data(lib, cin, cout, dims):
     n = int(np.prod(dims))
