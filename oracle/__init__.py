@@ -21,8 +21,9 @@ Functions and the passage each follows:
 * ``step``          - Sec. 3.1 fractional step (forces, semi-Lagrangian
                       advection, pressure correction) on the staggered grid,
                       plus explicit viscosity (Sec. 5 future-work item).
-* ``conv3d_*``, ``net_*``, ``adam`` - the learned warm start's network
-                      (not in the paper; definitions written out directly).
+* ``conv3d_*``, ``net_*``, ``adam``, ``round_bf16`` - the learned warm
+                      start's network (not in the paper; definitions written
+                      out directly; its activations are stored in bfloat16).
 """
 from __future__ import annotations
 
@@ -337,15 +338,33 @@ def split_params(theta, shapes):
     return out
 
 
-def net_forward(grid, x, theta, shapes):
-    """Conv-ReLU stack (ReLU after every layer but the last).  Returns (y, acts)."""
+def round_bf16(a) -> np.ndarray:
+    """Round to the nearest bfloat16 (8 significant bits, float32's exponent
+    range), ties to even, via float32 (as a float32 accumulator would hold the
+    value first).  Written from the format's definition: a value m * 2^e with
+    0.5 <= |m| < 1 keeps m rounded to a multiple of 2^-8; below float32's
+    normal range the spacing stays 2^-133.  Returns float64."""
+    v = np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+    m, e = np.frexp(v)
+    e = np.maximum(e, -125)  # float32 normals start at 2^-126 = 0.5 * 2^-125
+    return np.ldexp(np.rint(np.ldexp(v, 8 - e)), e - 8)
+
+
+def net_forward(grid, x, theta, shapes, act_bf16=False):
+    """Conv-ReLU stack (ReLU after every layer but the last).  Returns (y, acts).
+
+    act_bf16: store the input and every hidden activation in bfloat16, as the
+    network's definition has it (the convolutions themselves stay exact in
+    float64 here)."""
     Ws = split_params(theta, shapes)
-    acts = [_f64(x)]
+    acts = [round_bf16(x) if act_bf16 else _f64(x)]
     h = acts[0]
     for l, ((cin, cout), W) in enumerate(zip(shapes, Ws)):
         h = conv3d_fwd(grid, h, W, cin, cout)
         if l < len(shapes) - 1:
             h = np.maximum(h, 0.0)
+            if act_bf16:
+                h = round_bf16(h)
         acts.append(h)
     return acts[-1], acts
 

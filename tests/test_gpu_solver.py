@@ -11,6 +11,8 @@ Tolerances (derived in DESIGN.md, "Parity bars"):
   (the pressure-error bar); float64 iteration counts within 2 % + 2 of the
   oracle's (same algorithm, different summation order).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -306,6 +308,15 @@ def test_solve_256_mixed_full_size(lib):
     assert info64["status"] == 0
     assert true_relres(ref, b, x64) <= 1e-10 + relres_rounding(ref, b, x64)
     assert mean_removed_err(x64, truth) <= 1e-9
+    # the headline path: mixed + projected from the learned warm start
+    wpath = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_2504_03697_amd", "weights", "warmstart.npy")
+    xl, infol = lib.solve(A, bd, tol=1e-10, precision="mixed", formulation="projected",
+                          net=lib.Net(np.load(wpath)))
+    xl = host(xl)
+    assert infol["status"] == 0 and infol["used_fallback"] == 0 and infol["rel_residual"] <= 1e-10
+    assert true_relres(ref, b, xl) <= 1e-10 + relres_rounding(ref, b, xl)
+    assert mean_removed_err(xl, truth) <= 1e-9
     # the DIC-preconditioned solve (red-black order) at the same size
     for precision in ("mixed", "fp64"):
         xd, infod = lib.solve(A, bd, tol=1e-10, precision=precision, formulation="projected", precond="dic")

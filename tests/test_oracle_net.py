@@ -104,3 +104,25 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(th1, th - lr * g / (np.abs(g) + eps), rtol=1e-14, atol=1e-16)
     np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
     np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-13)
+
+
+def test_round_bf16_definition():
+    """bfloat16 rounding (the network's activation storage): exact cases of
+    round-to-nearest-even at 8 significant bits, sign symmetry, float32's
+    subnormal spacing, and agreement with a bit-level version (keep the top
+    16 bits of the float32 pattern after adding 0x7FFF plus the kept lsb)."""
+    r = oracle.round_bf16
+    u = 2.0**-7  # spacing just above 1
+    cases = {1.0: 1.0, 1 + u / 2: 1.0, 1 + 3 * u / 2: 1 + 2 * u, 1 + u: 1 + u, 3.0: 3.0,
+             -(1 + 3 * u / 2): -(1 + 2 * u), 2.0**-130: 2.0**-130, 1.5 * 2.0**-133: 2.0**-132,
+             2.5 * 2.0**-133: 2.0**-132, 0.0: 0.0}
+    got = r(np.array(list(cases.keys())))
+    np.testing.assert_array_equal(got, np.array(list(cases.values())))
+    rng = np.random.default_rng(5)
+    a = (rng.standard_normal(20000) * np.exp(rng.uniform(-60, 60, 20000))).astype(np.float32)
+    bits = a.view(np.uint32).astype(np.uint64)
+    bits = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16) << 16
+    want = bits.astype(np.uint32).view(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(r(a), want)
+    np.testing.assert_array_equal(r(r(a)), r(a))
+
