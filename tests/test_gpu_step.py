@@ -214,3 +214,31 @@ def test_previous_guess_validation(lib):
         lib.step(S, 0.005, net=net, guess="previous")
     with pytest.raises(ValueError):
         lib.step(S, 0.005, guess="last")
+
+
+@pytest.mark.parametrize("precision,precond,guess", [("fp64", "none", "zero"), ("mixed", "dic", "previous")])
+def test_resume_from_saved_state_bitwise(lib, precision, precond, guess):
+    """A cavity run has no state beyond cfd_state: 10 steps equal 5 steps,
+    a save of (u, v, w, p, t, step) to host memory, a fresh state loaded from
+    it, and 5 more steps, bit for bit."""
+    n, nu, dt = 16, 0.01, 0.005
+    kw = dict(tol=1e-10, precision=precision, formulation="projected", precond=precond, guess=guess)
+    S = lib.State(n, nu=nu, lid_u=1.0)
+    for _ in range(10):
+        lib.step(S, dt, **kw)
+    T = lib.State(n, nu=nu, lid_u=1.0)
+    for _ in range(5):
+        lib.step(T, dt, **kw)
+    saved = {f: host(getattr(T, f)).copy() for f in ("u", "v", "w", "p")}
+    t_saved, step_saved = T.c.t, T.c.step
+    del T
+    U = lib.State(n, nu=nu, lid_u=1.0)
+    for f, a in saved.items():
+        getattr(U, f).copy_(torch.from_numpy(a))
+    U.c.t, U.c.step = t_saved, step_saved
+    for _ in range(5):
+        lib.step(U, dt, **kw)
+    for f in ("u", "v", "w", "p"):
+        assert np.array_equal(host(getattr(U, f)), host(getattr(S, f))), f
+    assert U.c.t == S.c.t and U.c.step == S.c.step == 10
+
