@@ -35,7 +35,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cfd_oracle.c")
-_LIB = os.path.join(_HERE, "libcfd_oracle.so")
+# CFD_ORACLE_LIB: load a prebuilt copy instead (the sanitizer test builds
+# one with -fsanitize=address,undefined)
+_LIB_OVERRIDE = os.environ.get("CFD_ORACLE_LIB")
+_LIB = _LIB_OVERRIDE or os.path.join(_HERE, "libcfd_oracle.so")
 
 OK, ENOCONV, EBREAKDOWN, ENONFINITE = 0, -4, -5, -6
 
@@ -55,7 +58,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not _LIB_OVERRIDE and (not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
             build()
         lib = ctypes.CDLL(_LIB)
         i32, i64, dbl, vp = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
