@@ -101,7 +101,7 @@ int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, void *strea
 int cfd_rhs_prepare(cfd_csr_t A, double *b, void *stream);
 
 /* ------------------------------------------------------------------ */
-/* Solver (Sec. 3.1: conjugate gradients, here unpreconditioned)        */
+/* Solver (Sec. 3.1: conjugate gradients, unpreconditioned or with DIC) */
 /* ------------------------------------------------------------------ */
 
 typedef struct cfd_net *cfd_net_t;
