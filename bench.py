@@ -295,12 +295,21 @@ def cpu_baseline(n, b, iters_needed, budget_s):
     _, it, _, _ = oracle.cg(A, b, tol=0.0, max_iters=k)
     dt = time.perf_counter() - t
     per_iter = dt / it
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"oracle: {it} iterations in {dt:.1f} s on {cores} threads")
+    cores = oracle.threads()
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    log(f"oracle: {it} iterations in {dt:.1f} s on {cores} threads ({cpu})")
     return {"value": round(per_iter * iters_needed, 3), "unit": "s", "cores": cores, "kind": "oracle",
             "sample": f"first {it} FP64 CG iterations of one {n}^3 solve ({dt:.1f} s), scaled to the "
                       f"{iters_needed} iterations plain FP64 CG needs on that right-hand side",
-            "seconds_per_iter": round(per_iter, 5)}
+            "seconds_per_iter": round(per_iter, 5), "cpu": cpu}
 
 
 if __name__ == "__main__":

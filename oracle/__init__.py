@@ -95,6 +95,8 @@ def _load():
             f = getattr(lib, name)
             f.restype = None
             f.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp]
+        lib.ora_threads.restype = i32
+        lib.ora_threads.argtypes = []
         lib.ora_adam.restype = None
         lib.ora_adam.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i32]
         _lib = lib
@@ -330,6 +332,11 @@ def conv3d_bwd_weight(grid, X, dY, cin, cout):
     dW = np.empty(27 * cin * cout)
     _load().ora_conv3d_bwd_weight(nx, ny, nz, cin, cout, _p(X), _p(dY), _p(dW))
     return dW
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops run on."""
+    return int(_load().ora_threads())
 
 
 def split_params(theta, shapes):

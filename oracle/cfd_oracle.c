@@ -36,9 +36,13 @@
  * do not depend on the OpenMP thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads the parallel loops use (reported beside the timings). */
+int ora_threads(void) { return omp_get_max_threads(); }
 
 #define ORA_CHUNKS 256
 
