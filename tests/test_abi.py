@@ -44,3 +44,25 @@ def test_no_oracle_in_product_tree():
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "cfd_oracle" not in text, f
     assert os.path.isdir(os.path.join(root, "oracle"))
+
+
+def test_host_side_argument_checks():
+    """Arguments the library rejects on the host, before any device call
+    (this runs without a GPU): null pointers, empty grids, a non-positive
+    cell size, an out-of-range pin, and a grid whose CSR would overflow the
+    32-bit indices (N = 700: 7*700^3 > 2^31)."""
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    g = _lib.CfdGrid(4, 4, 4, 0.25)
+    assert lib.cfd_assemble(None, 0, None, ctypes.byref(out)) == _lib.CFD_EINVAL
+    assert lib.cfd_assemble(ctypes.byref(g), 0, None, None) == _lib.CFD_EINVAL
+    for bad in (_lib.CfdGrid(0, 4, 4, 0.25), _lib.CfdGrid(4, 4, -1, 0.25), _lib.CfdGrid(4, 4, 4, 0.0)):
+        assert lib.cfd_assemble(ctypes.byref(bad), 0, None, ctypes.byref(out)) == _lib.CFD_EINVAL
+    assert lib.cfd_assemble(ctypes.byref(g), 64, None, ctypes.byref(out)) == _lib.CFD_EINVAL
+    big = _lib.CfdGrid(700, 700, 700, 1.0 / 700)
+    assert lib.cfd_assemble(ctypes.byref(big), 0, None, ctypes.byref(out)) == _lib.CFD_EINVAL
+    assert b"32-bit" in lib.cfd_last_error()
+    assert not out.value
+    info = _lib.CfdSolveInfo()
+    assert lib.cfd_solve(None, None, None, 1e-10, None, None, ctypes.byref(info), None) == _lib.CFD_EINVAL
+    assert lib.cfd_spmv(None, 0, None, None, None) == _lib.CFD_EINVAL
