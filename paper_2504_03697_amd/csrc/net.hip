@@ -402,14 +402,27 @@ __global__ void __launch_bounds__(kBlock) wgrad_mfma(Geo g, const uint16_t *__re
         }
 }
 
-// grad[i] (+)= sum over waves of part[w][i], in wave order.
-__global__ void wgrad_reduce(const float *__restrict__ part, int64_t nwaves, int count, float *__restrict__ grad,
-                             int accumulate) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int64_t w = 0; w < nwaves; ++w) s += part[w * count + i];
-        grad[i] = accumulate ? grad[i] + (float)s : (float)s;
-    }
+// grad[i] (+)= sum over waves of part[w][i], in a fixed order: the waves in
+// kWgradSeg contiguous segments, each summed in wave order by one thread per
+// weight (consecutive weights in consecutive lanes, so the loads coalesce),
+// then the segment sums in segment order.
+constexpr int kWgradSeg = 64;
+__global__ void wgrad_reduce_seg(const float *__restrict__ part, int64_t nwaves, int count,
+                                 double *__restrict__ seg) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t w0 = nwaves * blockIdx.y / kWgradSeg, w1 = nwaves * (blockIdx.y + 1) / kWgradSeg;
+    double s = 0.0;
+    for (int64_t w = w0; w < w1; ++w) s += part[w * count + i];
+    seg[(int64_t)blockIdx.y * count + i] = s;
+}
+
+__global__ void wgrad_reduce(const double *__restrict__ seg, int count, float *__restrict__ grad, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double s = 0.0;
+    for (int k = 0; k < kWgradSeg; ++k) s += seg[(int64_t)k * count + i];
+    grad[i] = accumulate ? grad[i] + (float)s : (float)s;
 }
 
 // Partial sums of squares of a float64 vector (for rms normalisation).
@@ -539,6 +552,12 @@ static int wgrad_waves(int64_t n) {
     return grid_waves((n + 31) / 32) * 4;  // blocks * 4 waves
 }
 
+// Floats of the partial-sum buffer launch_wgrad needs for `count` weights:
+// one partial per wave, then kWgradSeg segment sums (doubles).
+static int64_t wgrad_part_floats(int64_t n, int count) {
+    return (int64_t)wgrad_waves(n) * count + 2 * (int64_t)kWgradSeg * count;
+}
+
 template <int CIN, int COUT>
 static void launch_wgrad(const Geo &g, const uint16_t *x, const uint16_t *dy, float *part, float *grad, int accumulate,
                          hipStream_t s) {
@@ -546,7 +565,10 @@ static void launch_wgrad(const Geo &g, const uint16_t *x, const uint16_t *dy, fl
     const int64_t nw = (int64_t)blocks * 4;
     hipLaunchKernelGGL((wgrad_mfma<CIN, COUT>), dim3(blocks), dim3(kBlock), 0, s, g, x, dy, part);
     const int count = 27 * CIN * COUT;
-    hipLaunchKernelGGL(wgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, s, (const float *)part, nw, count, grad,
+    double *seg = reinterpret_cast<double *>(part + nw * count);  // nw is even: 8-byte aligned
+    hipLaunchKernelGGL(wgrad_reduce_seg, dim3((count + 255) / 256, kWgradSeg), dim3(256), 0, s, (const float *)part,
+                       nw, count, seg);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, s, (const double *)seg, count, grad,
                        accumulate);
 }
 
@@ -614,7 +636,7 @@ static int net_ensure(cfd_net *N, const Geo &g, bool train) {
         CFD_HIP(hipMalloc(&N->dy, sizeof(uint16_t) * g.n));
         for (int i = 0; i < 2; ++i) CFD_HIP(hipMalloc(&N->dh[i], sizeof(uint16_t) * g.n * kC));
         CFD_HIP(hipMalloc(&N->dxp, sizeof(float) * npad * kC));
-        N->wpart_elems = (int64_t)wgrad_waves(g.n) * 27 * kC * kC;
+        N->wpart_elems = wgrad_part_floats(g.n, 27 * kC * kC);
         CFD_HIP(hipMalloc(&N->wpart, sizeof(float) * N->wpart_elems));
     }
     return CFD_OK;
@@ -905,9 +927,8 @@ extern "C" int cfd_conv3d_backward_weight(const cfd_grid *grid, int32_t cin, int
     if (rc != CFD_OK) return rc;
     if (!x || !dy || !dw) return fail(CFD_EINVAL, "conv3d: null pointer");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t nw = wgrad_waves(g.n);
     float *part;
-    CFD_HIP(hipMallocAsync((void **)&part, sizeof(float) * nw * 27 * cin * cout, s));
+    CFD_HIP(hipMallocAsync((void **)&part, sizeof(float) * wgrad_part_floats(g.n, 27 * cin * cout), s));
     if (cin == 1) launch_wgrad<1, 16>(g, x, dy, part, dw, 0, s);
     else if (cout == 16) launch_wgrad<16, 16>(g, x, dy, part, dw, 0, s);
     else launch_wgrad<16, 1>(g, x, dy, part, dw, 0, s);
