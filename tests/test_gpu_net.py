@@ -319,3 +319,20 @@ def test_trained_warm_start_effect(lib):
             rows.append((seed, prec, form, i1["iters"], i0["iters"]))
             assert i1["iters"] <= 1.1 * i0["iters"] + 2
     print("learned vs zero start (seed, precision, formulation, iters with net, iters from zero):", rows)
+
+
+def test_set_params_round_trip(lib):
+    """cfd_net_set_params / get_params: the weights read back are the ones
+    written, bit for bit, and a network whose weights were replaced predicts
+    exactly what a network created with those weights predicts."""
+    a, b = synth.net_init(11), synth.net_init(12)
+    net = lib.Net(a)
+    net.set_params(b)
+    assert np.array_equal(net.params(), np.asarray(b, dtype=np.float32))
+    dims = (19, 17, 11)
+    rhs = torch.from_numpy(synth.uniform_rhs(dims, 6)).cuda()
+    y1 = host(net.forward(dims, rhs))
+    y2 = host(lib.Net(b).forward(dims, rhs))
+    assert np.array_equal(y1, y2)
+    with pytest.raises(lib.CfdError):
+        net.set_params(np.zeros(3, dtype=np.float32))
