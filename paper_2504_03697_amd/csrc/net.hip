@@ -25,9 +25,10 @@
 // cells that clamp to each voxel.
 //
 // Backward weights: dW[t][ci][co] = sum_v X[clamp(v + d_t)][ci] dY[v][co] is
-// a GEMM with K = voxels; each wave accumulates all 27 taps over its chunks of
-// 32 voxels on the matrix cores and writes one partial sum, which a second
-// kernel reduces in a fixed order (deterministic, no atomics).
+// a GEMM with K = voxels; each workgroup marches its columns along z with
+// X's halo planes and dY's plane in LDS, its waves accumulate a share of the
+// 27 taps on the matrix cores, and it writes one partial sum, which two
+// more kernels reduce in a fixed order (deterministic, no atomics).
 #include "common.h"
 
 #include <cmath>
@@ -346,60 +347,131 @@ __global__ void __launch_bounds__(kBlock) fold_kernel(Geo g, const float *__rest
     }
 }
 
-// Weight gradient partial sums: every wave accumulates dW[t][ci][co] over
-// its chunks of 32 voxels (K = voxels) for all 27 taps.
+// Weight gradient marching along z (the columns and z ranges of
+// conv_fwd_z).  dW[t][ci][co] = sum_v X[clamp(v + d_t)][ci] dY[v][co] is an
+// MFMA product with K = voxels: a 32-voxel block is two rows of the 16 x 16
+// tile, and lane (m, grp) holds its voxels 8 grp .. 8 grp + 7.  The halo
+// planes of X sit in a 3-slot LDS ring (the next one loaded into registers
+// while a plane computes), dY's plane in LDS (zero outside the grid); both
+// operands are read from LDS.  Wave w owns the taps w, w + 4, ... and
+// accumulates them over its workgroup's items; each workgroup writes one
+// partial dW, which wgrad_reduce_* sum in a fixed order.
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(kBlock) wgrad_mfma(Geo g, const uint16_t *__restrict__ x,
-                                                     const uint16_t *__restrict__ dy, float *__restrict__ part) {
-    const int lane = threadIdx.x & 63;
+__global__ void __launch_bounds__(kBlock) wgrad_z(Geo g, int zc, const uint16_t *__restrict__ in,
+                                                  const uint16_t *__restrict__ dy, float *__restrict__ part) {
+    constexpr int kTaps = 7;  // taps per wave: wave + 4 j < 27
+    __shared__ __align__(16) uint16_t s_in[3 * kPlane * CIN];
+    __shared__ __align__(16) uint16_t s_dy[kTX * kTY * COUT];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int ml = lane & 15, grp = lane >> 4;
-    const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
-    f32x4 acc[27];
+    f32x4 acc[kTaps];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int64_t nchunks = (g.n + 31) / 32;
-    for (int64_t ch = wave; ch < nchunks; ch += nwaves) {
-        int vi[8], vj[8], vk[8];
-        bool ok[8];
-        u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < kTaps; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int ntx = (g.nx + kTX - 1) / kTX, nty = (g.ny + kTY - 1) / kTY, nzc = (g.nz + zc - 1) / zc;
+    const TileRange tr = tile_range((int64_t)ntx * nty * nzc);
+    for (int64_t item = tr.first; item < tr.end; item += tr.step) {
+        const int x0 = (int)(item % ntx) * kTX, y0 = (int)((item / ntx) % nty) * kTY;
+        const int z0 = (int)(item / ((int64_t)ntx * nty)) * zc;
+        const int z1 = min(z0 + zc, g.nz);
+        auto load = [&](int p, PlaneRegs<CIN> &R) {
+            const int64_t zoff = (int64_t)g.nx * g.ny * clampi(p, 0, g.nz - 1);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t v = ch * 32 + 8 * grp + e;
-            ok[e] = v < g.n;
-            const int64_t vv = ok[e] ? v : 0;
-            vi[e] = (int)(vv % g.nx);
-            vj[e] = (int)((vv / g.nx) % g.ny);
-            vk[e] = (int)(vv / ((int64_t)g.nx * g.ny));
-            if (ok[e] && ml < COUT) b[e] = dy[v * COUT + ml];
-        }
-        const bf16x8 B = __builtin_bit_cast(bf16x8, b);
+            for (int q = 0; q < PlaneRegs<CIN>::kN; ++q) {
+                const int c = threadIdx.x + q * kBlock;
+                const int h = CIN == 16 ? (c >> 1) : c;
+                const int hh = min(h, kPlane - 1);
+                const int hx = hh % kPX, hy = hh / kPX;
+                const int64_t src = zoff + clampi(x0 + hx - 1, 0, g.nx - 1) +
+                                    (int64_t)g.nx * clampi(y0 + hy - 1, 0, g.ny - 1);
+                if constexpr (CIN == 16) R.v[q] = *reinterpret_cast<const u16x8 *>(in + src * 16 + 8 * (c & 1));
+                else R.v[q] = in[src];
+            }
+        };
+        auto commit = [&](int p, const PlaneRegs<CIN> &R) {
+            const int slot = (p + 3) % 3;
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dx = t % 3 - 1, dyy = (t / 3) % 3 - 1, dz = t / 9 - 1;
-            u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (ml < CIN) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if (!ok[e]) continue;
-                    const int64_t src = (int64_t)clampi(vi[e] + dx, 0, g.nx - 1) +
-                                        (int64_t)g.nx * ((int64_t)clampi(vj[e] + dyy, 0, g.ny - 1) +
-                                                         (int64_t)g.ny * clampi(vk[e] + dz, 0, g.nz - 1));
-                    a[e] = x[src * CIN + ml];
+            for (int q = 0; q < PlaneRegs<CIN>::kN; ++q) {
+                const int c = threadIdx.x + q * kBlock;
+                if constexpr (CIN == 16) {
+                    if (c < kPlane * 2) reinterpret_cast<u16x8 *>(s_in)[slot * kPlane * 2 + c] = R.v[q];
+                } else {
+                    if (c < kPlane) s_in[slot * kPlane + c] = R.v[q];
                 }
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), B, acc[t], 0, 0, 0);
+        };
+        PlaneRegs<CIN> R;
+        for (int p = z0 - 1; p <= z0 + 1; ++p) {
+            load(p, R);
+            commit(p, R);
+        }
+        load(z0 + 2, R);
+        for (int z = z0; z < z1; ++z) {
+            // dY of the tile's plane z, zero outside the grid
+            if constexpr (COUT == 16) {
+                for (int c = threadIdx.x; c < kTX * kTY * 2; c += kBlock) {
+                    const int v = c >> 1, x = x0 + v % kTX, y = y0 + v / kTX;
+                    u16x8 val = {0, 0, 0, 0, 0, 0, 0, 0};
+                    if (x < g.nx && y < g.ny)
+                        val = *reinterpret_cast<const u16x8 *>(
+                            dy + ((int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z)) * 16 + 8 * (c & 1));
+                    reinterpret_cast<u16x8 *>(s_dy)[c] = val;
+                }
+            } else {
+                for (int v = threadIdx.x; v < kTX * kTY; v += kBlock) {
+                    const int x = x0 + v % kTX, y = y0 + v / kTX;
+                    s_dy[v] = (x < g.nx && y < g.ny)
+                                  ? dy[(int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z)]
+                                  : (uint16_t)0;
+                }
+            }
+            __syncthreads();
+#pragma unroll 1
+            for (int kb = 0; kb < kTX * kTY / 32; ++kb) {
+                u16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int v = 32 * kb + 8 * grp + e;  // voxel of the tile, x fastest
+                    if (ml < COUT) b[e] = s_dy[v * COUT + ml];
+                }
+                const bf16x8 B = __builtin_bit_cast(bf16x8, b);
+#pragma unroll
+                for (int j = 0; j < kTaps; ++j) {
+                    const int t = wave + 4 * j;
+                    if (t < 27) {
+                        const int dx = t % 3 - 1, dyy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+                        const int slot = (z + dz + 3) % 3;
+                        u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int v = 32 * kb + 8 * grp + e;
+                            const int h = (v % kTX + 1 + dx) + kPX * (v / kTX + 1 + dyy);
+                            if (ml < CIN) a[e] = s_in[(slot * kPlane + h) * CIN + ml];
+                        }
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), B, acc[j], 0,
+                                                                         0, 0);
+                    }
+                }
+            }
+            __syncthreads();  // every wave is done with the slot of plane z-1 and with s_dy
+            if (z + 1 < z1) {
+                commit(z + 2, R);
+                load(z + 3, R);
+            }
+            __syncthreads();
         }
     }
-    // lane holds D[ci = 4*grp + q][co = lane & 15]
-    float *dst = part + wave * (27 * CIN * COUT);
+    // lane holds D[ci = 4 grp + q][co = ml] of each of its taps
+    float *dst = part + (int64_t)blockIdx.x * (27 * CIN * COUT);
 #pragma unroll
-    for (int t = 0; t < 27; ++t)
+    for (int j = 0; j < kTaps; ++j) {
+        const int t = wave + 4 * j;
+        if (t >= 27) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int ci = 4 * grp + q, co = ml;
-            if (ci < CIN && co < COUT) dst[((int64_t)t * CIN + ci) * COUT + co] = acc[t][q];
+            if (ci < CIN && co < COUT) dst[((int64_t)t * CIN + ci) * COUT + co] = acc[j][q];
         }
+    }
 }
 
 // grad[i] (+)= sum over waves of part[w][i], in a fixed order: the waves in
@@ -503,6 +575,29 @@ __global__ void adam_kernel(float *__restrict__ th, float *__restrict__ m, float
 
 // ---------------------------------------------------------------- host side
 
+// Work items and grid of the z-marching kernels (conv_fwd_z, wgrad_z): z
+// ranges sized so the items about fill the resident workgroups.
+struct ZGrid {
+    int zc, blocks;
+};
+template <class K>
+static ZGrid zgrid(const Geo &g, K kernel) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    Device d;
+    if (device_info(&d) != CFD_OK) d.cus = 256;
+    const int64_t resident = (int64_t)per_cu * d.cus;
+    const int64_t ncol = (int64_t)((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY);
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(g.nz, (resident + ncol - 1) / ncol));
+    ZGrid z;
+    z.zc = (int)((g.nz + want - 1) / want);
+    const int64_t items = ncol * ((g.nz + z.zc - 1) / z.zc);
+    z.blocks = (int)std::min<int64_t>(items, resident);
+    if (z.blocks > kXcd) z.blocks -= z.blocks % kXcd;
+    return z;
+}
+
 static int grid_waves(int64_t work_items_per_wave_units) {
     Device d;
     if (device_info(&d) != CFD_OK) d.cus = 256;
@@ -513,25 +608,8 @@ static int grid_waves(int64_t work_items_per_wave_units) {
 template <int CIN, int COUT, int MODE, bool OUT_BF16>
 static void launch_conv(const Geo &g, const uint16_t *in, const uint16_t *frag, void *out, int relu, hipStream_t s) {
     if constexpr (MODE == FWD) {
-        // z ranges sized so the work items about fill the resident workgroups
-        static const int per_cu = [] {
-            int nb = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, conv_fwd_z<CIN, COUT, OUT_BF16>, kBlock, 0) !=
-                    hipSuccess ||
-                nb < 1)
-                nb = 1;
-            return nb;
-        }();
-        Device d;
-        if (device_info(&d) != CFD_OK) d.cus = 256;
-        const int64_t resident = (int64_t)per_cu * d.cus;
-        const int64_t ncol = (int64_t)((g.nx + kTX - 1) / kTX) * ((g.ny + kTY - 1) / kTY);
-        const int64_t want = std::max<int64_t>(1, std::min<int64_t>(g.nz, (resident + ncol - 1) / ncol));
-        const int zc = (int)((g.nz + want - 1) / want);
-        const int64_t items = ncol * ((g.nz + zc - 1) / zc);
-        int blocks = (int)std::min<int64_t>(items, resident);
-        if (blocks > kXcd) blocks -= blocks % kXcd;
-        hipLaunchKernelGGL((conv_fwd_z<CIN, COUT, OUT_BF16>), dim3(blocks), dim3(kBlock), 0, s, g, zc, in,
+        const ZGrid z = zgrid(g, conv_fwd_z<CIN, COUT, OUT_BF16>);
+        hipLaunchKernelGGL((conv_fwd_z<CIN, COUT, OUT_BF16>), dim3(z.blocks), dim3(kBlock), 0, s, g, z.zc, in,
                            (const u16x8 *)frag, out, relu);
         return;
     }
@@ -548,26 +626,30 @@ static void launch_pack(const float *W, int cin_f, int cout_f, int trans, uint16
     else hipLaunchKernelGGL(pack_weights<1>, dim3(2), dim3(256), 0, s, W, cin_f, cout_f, trans, frag);
 }
 
-static int wgrad_waves(int64_t n) {
-    return grid_waves((n + 31) / 32) * 4;  // blocks * 4 waves
+// Partial weight gradients: at most this many (one per workgroup of wgrad_z).
+static int64_t wgrad_parts(int64_t) {
+    Device d;
+    if (device_info(&d) != CFD_OK) d.cus = 256;
+    return (int64_t)d.cus * 8;
 }
 
 // Floats of the partial-sum buffer launch_wgrad needs for `count` weights:
-// one partial per wave, then kWgradSeg segment sums (doubles).
+// one partial per workgroup, then kWgradSeg segment sums (doubles).
 static int64_t wgrad_part_floats(int64_t n, int count) {
-    return (int64_t)wgrad_waves(n) * count + 2 * (int64_t)kWgradSeg * count;
+    return wgrad_parts(n) * count + 2 * (int64_t)kWgradSeg * count + 2;
 }
 
 template <int CIN, int COUT>
 static void launch_wgrad(const Geo &g, const uint16_t *x, const uint16_t *dy, float *part, float *grad, int accumulate,
                          hipStream_t s) {
-    const int blocks = grid_waves((g.n + 31) / 32);
-    const int64_t nw = (int64_t)blocks * 4;
-    hipLaunchKernelGGL((wgrad_mfma<CIN, COUT>), dim3(blocks), dim3(kBlock), 0, s, g, x, dy, part);
+    const ZGrid z = zgrid(g, wgrad_z<CIN, COUT>);
+    const int64_t nparts = std::min<int64_t>(z.blocks, wgrad_parts(g.n));
+    hipLaunchKernelGGL((wgrad_z<CIN, COUT>), dim3(nparts), dim3(kBlock), 0, s, g, z.zc, x, dy, part);
     const int count = 27 * CIN * COUT;
-    double *seg = reinterpret_cast<double *>(part + nw * count);  // nw is even: 8-byte aligned
+    // segment sums after the partials, 8-byte aligned
+    double *seg = reinterpret_cast<double *>(part + ((nparts * count + 1) & ~(int64_t)1));
     hipLaunchKernelGGL(wgrad_reduce_seg, dim3((count + 255) / 256, kWgradSeg), dim3(256), 0, s, (const float *)part,
-                       nw, count, seg);
+                       nparts, count, seg);
     hipLaunchKernelGGL(wgrad_reduce, dim3((count + 255) / 256), dim3(256), 0, s, (const double *)seg, count, grad,
                        accumulate);
 }

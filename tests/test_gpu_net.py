@@ -104,7 +104,20 @@ def test_conv_backward_weight(lib, cin, cout, dims):
     ref = oracle.conv3d_bwd_weight(dims, x, dy, cin, cout)
     absref = oracle.conv3d_bwd_weight(dims, np.abs(x), np.abs(dy), cin, cout)
     dw = host(lib.conv3d_backward_weight(dims, cin, cout, bits(x), bits(dy)))
-    # per-wave float32 partial sums, then a float64 sum of the partials
+    # per-workgroup float32 partial sums, then a float64 sum of the partials
+    assert np.all(np.abs(dw - ref) <= gamma(n + 64) * absref * 1.01 + 1e-30)
+
+
+@pytest.mark.parametrize("cin,cout", SHAPES)
+@pytest.mark.parametrize("dims", [(130, 66, 40), (33, 47, 5)])
+def test_conv_backward_weight_many_columns(lib, cin, cout, dims):
+    """The weight gradient on grids of many 16 x 16 columns and z ranges."""
+    n = int(np.prod(dims))
+    x = synth.bf16_values(n * cin, 7)
+    dy = synth.bf16_values(n * cout, 8)
+    ref = oracle.conv3d_bwd_weight(dims, x, dy, cin, cout)
+    absref = oracle.conv3d_bwd_weight(dims, np.abs(x), np.abs(dy), cin, cout)
+    dw = host(lib.conv3d_backward_weight(dims, cin, cout, bits(x), bits(dy)))
     assert np.all(np.abs(dw - ref) <= gamma(n + 64) * absref * 1.01 + 1e-30)
 
 
