@@ -38,29 +38,30 @@ def log(msg):
 def a_kernel_bytes(n, nnz, mixed):
     """Algorithmic bytes of one launch of the CG SpMV kernel (normal mode).
 
-    CSR: row pointers 4(n+1), columns 4 nnz, values 4 or 8 nnz.
+    CSR: row pointers 4(n+1), columns 4 nnz, values 4 nnz (both kernels read
+    the float32 copy of the values, which are small integers and exact).
     Vectors per row: read r and p_old, write p_new and q (float32 in the
     mixed kernel, float64 otherwise); the float64 kernel also reads and
     writes x (the mixed path applies its queued x updates in the vector
     kernel that follows).
     """
     w = 4 if mixed else 8
-    return 4 * (n + 1) + nnz * (4 + w) + 4 * w * n + (0 if mixed else 16 * n)
+    return 4 * (n + 1) + nnz * 8 + 4 * w * n + (0 if mixed else 16 * n)
 
 
-def s_product_bytes(n3):
+def s_product_bytes(n3, w=4):
     """Algorithmic bytes of one product with the Schur complement on an N^3
-    grid in red-black order (projected formulation, float32 values and
-    vectors): the red sweep reads its rows' CSR (row pointers, columns, values
-    = diagonal + in-domain neighbours), z and p_old of the black cells and
-    writes y and the new direction; the black sweep reads its rows' CSR, the
-    direction and the gathered y, and writes q."""
+    grid in red-black order (projected formulation, float32 values, vectors
+    of w bytes): the red sweep reads its rows' CSR (row pointers, columns,
+    values = diagonal + in-domain neighbours), z and p_old of the black cells
+    and writes y and the new direction; the black sweep reads its rows' CSR,
+    the direction and the gathered y, and writes q."""
     n = n3 ** 3
     nr = (n + 1) // 2
     nb = n - nr
     edges = 3 * n3 * n3 * (n3 - 1)
-    red = 4 * (nr + 1) + 8 * (nr + edges) + 8 * nb + 4 * nr + 4 * nb
-    black = 4 * (nb + 1) + 8 * (nb + edges) + 4 * nb + 4 * nr + 4 * nb
+    red = 4 * (nr + 1) + 8 * (nr + edges) + 2 * w * nb + w * nr + w * nb
+    black = 4 * (nb + 1) + 8 * (nb + edges) + w * nb + w * nr + w * nb
     return red + black
 
 
@@ -171,10 +172,14 @@ def main():
              "rel_residual_max": max(i["rel_residual"] for i in out)}
         key = "a_kernel_ms" if precond == "none" else "s_product_ms"  # S product: the red + the black sweep
         d[key] = round(float(np.mean([i["spmv_ms"] for i in out if i["spmv_samples"]])), 5)
-        if precond != "none" and precision == "mixed" and form == "projected" and d[key] > 0:
-            sb = s_product_bytes(n)
+        if precond != "none" and form == "projected" and d[key] > 0:
+            sb = s_product_bytes(n, 4 if precision == "mixed" else 8)
             d["s_product_bytes"] = sb
             d["s_product_gbs"] = round(sb / (d[key] * 1e-3) / 1e9, 1)
+        elif precond == "none" and precision == "fp64" and d[key] > 0:
+            ab = a_kernel_bytes(A.n, A.nnz, False)
+            d["a_kernel_bytes"] = ab
+            d["a_kernel_gbs"] = round(ab / (d[key] * 1e-3) / 1e9, 1)
         log(f"{precision} {form}{' +net' if use_net else ''}{' +' + precond if precond != 'none' else ''}: "
             f"{d['ms_per_solve']:.1f} ms/solve iters {d['iters']}")
         return d

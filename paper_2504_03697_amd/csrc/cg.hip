@@ -79,8 +79,7 @@ struct CgState {
 struct SolveArgs {
     int64_t n;
     const int32_t *rp, *col;
-    const double *v64;
-    const float *v32;
+    const float *v32;       // matrix values: small integers, exact in float32
     double tol, ru_delta;
     int32_t max_iters;
     int32_t Ga, Gb, Gf;
@@ -230,10 +229,7 @@ __device__ inline bool is_pin_nb(const SolveArgs &a, int64_t i) {
 // that A_neu x = c with x_pin = b_pin is the pinned solution.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
-    typedef typename std::conditional<MIXED, float, double>::type VT;
-    __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) VT s_val[kSlabLds];
-    __shared__ double red[kBlock / 64];
+    CG_SHARED(float);
     double gamma = 1.0;
     int fallback = 0;
     const double *guess = a.x0;
@@ -262,8 +258,7 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
         if (a.y) return (j == a.pin) ? 0.0 : gamma * guess[j];
         return guess[j];
     };
-    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
-    csr_sweep<VT>(a.rp, a.col, val, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
         double acc = 0.0;
         if (have) acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, xg), xg);
         const double bi = a.b[i];
@@ -434,9 +429,12 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
 }
 
 // A kernel, float64.  Normal: x += alpha p_old; p = r + beta p_old; q = A p.
-// Init/refresh: (fold x) p = r; q = A p.
+// Init/refresh: (fold x) p = r; q = A p.  The matrix values come from the
+// float32 copy: they are small integers, so each float64 product, and the
+// result, is bit-identical to the one with the float64 copy, at 4 B per entry
+// less.  The same holds for every kernel of the solver that reads values.
 __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
-    CG_SHARED(double);
+    CG_SHARED(float);
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
     if (st.done || st.pending) {
@@ -461,7 +459,7 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     const double beta = D.beta;
     double pq = 0.0;
     auto wg = [&](int32_t j) -> double { return normal ? fma(beta, pold[j], a.r[j]) : a.r[j]; };
-    csr_sweep<double>(a.rp, a.col, a.v64, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
         const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, wg), wg);
         const double wi = wg((int32_t)i);
         if (fold && alpha != 0.0) store_stream(a.x + i, folded64(a, i, alpha, pold));
@@ -668,10 +666,7 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
 // never gathers x), so no workgroup can see a half-updated x here.
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
-    typedef typename std::conditional<MIXED, float, double>::type VT;
-    __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) VT s_val[kSlabLds];
-    __shared__ double red[kBlock / 64];
+    CG_SHARED(float);
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
     if (st.done || !st.pending) {
@@ -684,9 +679,8 @@ __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
         if constexpr (MIXED) return folded32(a, st, j);
         else return folded64(a, j, alpha, p64);
     };
-    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
     double rr = 0.0, rp = 0.0;
-    csr_sweep<VT>(a.rp, a.col, val, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
         const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, xg), xg);
         const double ri = a.c[i] - acc;
         a.r[i] = ri;
@@ -761,10 +755,16 @@ struct Grids {
     int a64, f64, a32, f32;
 };
 
+// Workgroups per CU of the float64 A kernel: measured at 256^3 (full solves,
+// per-launch time) 0.50 ms at 4 per CU, 0.46 at 5, 0.43 at 6 and 0.62 at 7,
+// the most that fit; past 6 the float64 neighbour planes it gathers no
+// longer stay in the XCD's L2.
+constexpr int kA64PerCu = 6;
+
 static const Grids &solver_grids() {
     static Grids g = [] {
         Grids r;
-        r.a64 = resident_per_cu(cg_a64);
+        r.a64 = std::min(resident_per_cu(cg_a64), kA64PerCu);
         r.f64 = std::min(resident_per_cu(cg_init<false>), resident_per_cu(cg_refresh<false>));
         r.a32 = resident_per_cu(cg_a32);
         r.f32 = std::min(std::min(resident_per_cu(cg_init<true>), resident_per_cu(cg_refresh<true>)),
@@ -803,7 +803,6 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.n = A->n;
     a.rp = A->rp;
     a.col = A->col;
-    a.v64 = A->val64;
     a.v32 = A->val32;
     a.tol = tol;
     a.ru_delta = delta;
@@ -1495,7 +1494,7 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
     typedef typename std::conditional<MIXED, f32x2, f64x2>::type VT2;
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) VT s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];  // exact values (small integers)
     __shared__ double red[kBlock / 64];
     const RbState st = a.S[t & 1];
     RbState *out = &a.S[(t + 1) & 1];
@@ -1534,7 +1533,6 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
     VT *z = MIXED ? (VT *)a.z32 : (VT *)a.z64;
     const RbDir<MIXED> dir{a, pold, cf, D.inv_s, normal, normal || (MIXED && st.cg.mode == MODE_REFRESH)};
     VT *y = MIXED ? (VT *)a.y32 : (VT *)a.y64;
-    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
     // black cell k = p: its z and p_old, a tile ahead
     auto own = [&](int64_t k) -> VT2 {
         VT2 o;
@@ -1542,9 +1540,9 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
         o.y = (k < a.nb && dir.use_p) ? pold[k] : VT(0);
         return o;
     };
-    csr_stream_rows<VT>(a.rp, a.col, val, 0, a.nr, s_col, s_val, own, [&](int64_t p, int rs, int re, VT2 o) {
+    csr_stream_rows<float>(a.rp, a.col, a.v32, 0, a.nr, s_col, s_val, own, [&](int64_t p, int rs, int re, VT2 o) {
         const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return dir.w(c - a.nr); });
-        y[p] = acc / s_val[rs];
+        y[p] = acc / (VT)s_val[rs];
         if (p < a.nb) {
             const VT wk = dir.use_p ? (VT)fma(dir.cf, o.y, o.x) : o.x;
             if (!normal) store_stream(z + p, o.x);
@@ -1559,7 +1557,7 @@ template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) VT s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];  // exact values (small integers)
     __shared__ double red[kBlock / 64];
     const RbState st = a.S[t & 1];
     RbState *out = &a.S[(t + 1) & 1];
@@ -1570,13 +1568,12 @@ __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
     const VT *pnew = (const VT *)rb_dir<MIXED>(a, st.cg.pcur, true);
     VT *q = MIXED ? (VT *)a.q32 : (VT *)a.q64;
     const VT *y = MIXED ? (const VT *)a.y32 : (const VT *)a.y64;
-    const VT *val = MIXED ? (const VT *)a.v32 : (const VT *)a.v64;
     double pq = 0.0;
     auto own = [&](int64_t p) { return pnew[p - a.nr]; };
-    csr_stream_rows<VT>(a.rp, a.col, val, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT wk) {
+    csr_stream_rows<float>(a.rp, a.col, a.v32, a.nr, a.n, s_col, s_val, own, [&](int64_t p, int rs, int re, VT wk) {
         const int64_t k = p - a.nr;
         const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return y[c]; });
-        const VT qk = fma(s_val[rs], wk, -acc);
+        const VT qk = fma((VT)s_val[rs], wk, -acc);
         store_stream(q + k, qk);
         pq = fma((double)wk, (double)qk, pq);
     });
@@ -1789,10 +1786,14 @@ __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     }
 }
 
-// Workgroups per CU of the red sweep's normal instance: measured at 256^3,
+// Workgroups per CU of the red sweep's normal mixed instance: measured at 256^3,
 // more resident workgroups make it slower (185 us at 8 per CU against 145 us
 // at 7), the gathers of the black vectors thrashing the XCD's L2.
 constexpr int kRbRedPerCu = 7;
+// Workgroups per CU of both float64 sweeps, measured the same way (FP64 DIC
+// solve at 256^3): 372 ms at 5 per CU, 378-380 ms at 6 or 7 (8 for the
+// black sweep).
+constexpr int kRb64PerCu = 5;
 
 // Host driver of the preconditioned solve (options already validated).
 static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts &opts,
@@ -1819,7 +1820,6 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     g.n = n;
     g.rp = A->rp;
     g.col = A->col;
-    g.v64 = A->val64;
     g.v32 = A->val32;
     g.pin = A->pin;
     g.proj = proj ? 1 : 0;
@@ -1861,9 +1861,9 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     static const int k2_per_cu[2] = {resident_per_cu(rb_k2<false>), resident_per_cu(rb_k2<true>)};
     static const int f_per_cu = std::min(std::min(resident_per_cu(rb_f1), resident_per_cu(rb_f2)),
                                          std::min(resident_per_cu(rb_init_red), resident_per_cu(rb_init_black)));
-    a.G1 = grid_tiles(nr, std::min(k1_per_cu[mixed], kRbRedPerCu));
+    a.G1 = grid_tiles(nr, std::min(k1_per_cu[mixed], mixed ? kRbRedPerCu : kRb64PerCu));
     const int G1g = grid_tiles(nr, k1g_per_cu[mixed]);
-    a.G2 = grid_tiles(nb, k2_per_cu[mixed]);
+    a.G2 = grid_tiles(nb, mixed ? k2_per_cu[mixed] : std::min(k2_per_cu[mixed], kRb64PerCu));
     a.Gf1 = grid_tiles(nr, f_per_cu);
     a.Gf2 = grid_tiles(nb, f_per_cu);
     a.Gv = grid_vec(nb);
