@@ -311,10 +311,23 @@ def cpu_baseline(n, b, iters_needed, budget_s):
     except OSError:
         pass
     log(f"oracle: {it} iterations in {dt:.1f} s on {cores} threads ({cpu})")
+    # the same on one thread, a shorter sample (the sums have a fixed order, so
+    # the iterates are the same bits)
+    oracle.set_threads(1)
+    try:
+        k1 = int(max(3, min(200, 0.25 * budget_s / max(per_iter * cores, 1e-6))))
+        t = time.perf_counter()
+        _, it1, _, _ = oracle.cg(A, b, tol=0.0, max_iters=k1)
+        dt1 = time.perf_counter() - t
+    finally:
+        oracle.set_threads(cores)
+    log(f"oracle: {it1} iterations in {dt1:.1f} s on 1 thread")
     return {"value": round(per_iter * iters_needed, 3), "unit": "s", "cores": cores, "kind": "oracle",
             "sample": f"first {it} FP64 CG iterations of one {n}^3 solve ({dt:.1f} s), scaled to the "
                       f"{iters_needed} iterations plain FP64 CG needs on that right-hand side",
-            "seconds_per_iter": round(per_iter, 5), "cpu": cpu}
+            "seconds_per_iter": round(per_iter, 5), "cpu": cpu,
+            "one_thread": {"value": round(dt1 / it1 * iters_needed, 3), "seconds_per_iter": round(dt1 / it1, 5),
+                           "sample": f"first {it1} iterations ({dt1:.1f} s), scaled the same way"}}
 
 
 if __name__ == "__main__":

@@ -97,6 +97,8 @@ def _load():
             f.argtypes = [i32, i32, i32, i32, i32, vp, vp, vp]
         lib.ora_threads.restype = i32
         lib.ora_threads.argtypes = []
+        lib.ora_set_threads.restype = None
+        lib.ora_set_threads.argtypes = [i32]
         lib.ora_adam.restype = None
         lib.ora_adam.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i32]
         _lib = lib
@@ -337,6 +339,12 @@ def conv3d_bwd_weight(grid, X, dY, cin, cout):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops run on."""
     return int(_load().ora_threads())
+
+
+def set_threads(t: int) -> None:
+    """Run the parallel loops on t threads (timings only: the sums have a
+    fixed order, so results do not depend on it)."""
+    _load().ora_set_threads(int(t))
 
 
 def split_params(theta, shapes):

@@ -44,6 +44,12 @@
 /* Threads the parallel loops use (reported beside the timings). */
 int ora_threads(void) { return omp_get_max_threads(); }
 
+/* Set that thread count (timings only: every sum below runs in a fixed
+ * order that does not depend on it, so the results do not change). */
+void ora_set_threads(int t) {
+    if (t > 0) omp_set_num_threads(t);
+}
+
 #define ORA_CHUNKS 256
 
 /* ------------------------------------------------------------------ */

@@ -18,7 +18,8 @@ def test_algorithmic_bytes():
     import bench
     n, nnz = 256**3, 7 * 256**3 - 6 * 256**2 - 6
     assert bench.a_kernel_bytes(n, nnz, True) == 4 * (n + 1) + 8 * nnz + 16 * n == 1271922644
-    assert bench.a_kernel_bytes(n, nnz, False) == 4 * (n + 1) + 12 * nnz + 48 * n
+    # the float64 kernel reads the float32 copy of the (integer) matrix values too
+    assert bench.a_kernel_bytes(n, nnz, False) == 4 * (n + 1) + 8 * nnz + 48 * n == 1808793556
     assert bench.spmv_bytes(n, nnz, 4) == 4 * (n + 1) + 8 * nnz + 8 * n
     assert len(bench.kernel_source_sha()) == 16
 
@@ -41,3 +42,5 @@ def test_s_product_bytes_match_the_matrix():
         nr, nb = int(red.sum()), int((~red).sum())
         want = (4 * (nr + 1) + 8 * nnz_r + 8 * nb + 4 * nr + 4 * nb) + (4 * (nb + 1) + 8 * nnz_b + 4 * nb + 4 * nr + 4 * nb)
         assert bench.s_product_bytes(N) == want
+        want64 = (4 * (nr + 1) + 8 * nnz_r + 16 * nb + 8 * nr + 8 * nb) + (4 * (nb + 1) + 8 * nnz_b + 8 * nb + 8 * nr + 8 * nb)
+        assert bench.s_product_bytes(N, 8) == want64

@@ -186,6 +186,23 @@ def test_cg_zero_rhs_and_warm_start():
     assert st == oracle.OK and it == 0 and rr <= 1e-10
 
 
+def test_cg_independent_of_thread_count():
+    """Every oracle sum runs in a fixed order, so the thread count the
+    timings use changes no bit of the result."""
+    A = oracle.assemble(14, 0)
+    b = oracle.rhs_prepare(synth.uniform_rhs(14, 3), 0)
+    t0 = oracle.threads()
+    try:
+        oracle.set_threads(1)
+        assert oracle.threads() == 1
+        x1, it1, rr1, _ = oracle.cg(A, b, tol=1e-10)
+        oracle.set_threads(3)
+        x3, it3, rr3, _ = oracle.cg(A, b, tol=1e-10)
+    finally:
+        oracle.set_threads(t0)
+    assert it1 == it3 and rr1 == rr3 and np.array_equal(x1, x3)
+
+
 def test_cg_error_codes():
     A = oracle.assemble(8, 0)
     b = oracle.rhs_prepare(synth.uniform_rhs(8, 2), 0)
