@@ -112,7 +112,9 @@ enum { CFD_GUESS_ZERO = 0, CFD_GUESS_PREVIOUS = 1 };
 enum { CFD_PRECOND_NONE = 0, CFD_PRECOND_DIC_RB = 1 };
 
 typedef struct cfd_solve_opts {
-    int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout.
+    int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout (the
+                            matrix values are read from the float32 copy:
+                            they are exact, so every product is the same).
                             CFD_PREC_MIXED: float32 matrix values, float32
                             SpMV and vector updates; float64 dot products,
                             step lengths, solution accumulation and true
