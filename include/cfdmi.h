@@ -158,8 +158,8 @@ typedef struct cfd_solve_opts {
                             products with S, and the stopping test is the
                             same ||b - A x|| <= tol ||b||.  Both precisions
                             and formulations, x0 and the network apply; the
-                            red-black copy of the matrix (float64 and
-                            float32) is built on the first such solve of
+                            red-black copy of the matrix (float32 values,
+                            exact) is built on the first such solve of
                             each formulation and kept with the handle.      */
     int32_t reserved_;
 } cfd_solve_opts;

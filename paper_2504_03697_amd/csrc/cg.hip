@@ -990,8 +990,7 @@ struct RbMatrix {
     int gmax = 0;
     int32_t *perm = nullptr, *iperm = nullptr;  // natural -> red-black, and back
     int32_t *rp = nullptr, *col = nullptr;      // CSR in red-black order, diagonal first
-    double *v64 = nullptr;
-    float *v32 = nullptr;
+    float *v32 = nullptr;                       // values: small integers, exact in float32
     double *d64 = nullptr;                      // diagonal of S (black rows)
     float *d32 = nullptr;
     // solve buffers; black length unless noted
@@ -1014,7 +1013,7 @@ struct RbState {
 
 void rb_free(RbMatrix *m) {
     if (!m) return;
-    void *pp[] = {m->perm, m->iperm, m->rp, m->col, m->v64, m->v32, m->d64, m->d32, m->bp, m->bS, m->xb,
+    void *pp[] = {m->perm, m->iperm, m->rp, m->col, m->v32, m->d64, m->d32, m->bp, m->bS, m->xb,
                   m->r64, m->y64, m->yb, m->z64, m->p64[0], m->p64[1], m->q64, m->z32, m->ring32,
                   m->q32, m->y32, m->part, m->S};
     for (void *p : pp) if (p) (void)hipFree(p);
@@ -1028,13 +1027,12 @@ void rb_free(RbMatrix *m) {
 // singular Neumann matrix.
 __global__ void __launch_bounds__(kBlock) rb_fill(int64_t n, int nx, int ny, int nz, int64_t pin,
                                                   const int32_t *perm, const int32_t *iperm, const int32_t *rp,
-                                                  int32_t *col, double *v64, float *v32) {
+                                                  int32_t *col, float *v32) {
     for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
         const int64_t m = iperm[p];
         int64_t e = rp[p];
         if (m == pin) {
             col[e] = (int32_t)p;
-            v64[e] = 1.0;
             v32[e] = 1.0f;
             continue;
         }
@@ -1045,13 +1043,11 @@ __global__ void __launch_bounds__(kBlock) rb_fill(int64_t n, int nx, int ny, int
         int deg = 0;
         for (int q = 0; q < 6; ++q) deg += cand[q] >= 0;
         col[e] = (int32_t)p;
-        v64[e] = (double)deg;
         v32[e] = (float)deg;
         ++e;
         for (int q = 0; q < 6; ++q) {
             if (cand[q] < 0 || cand[q] == pin) continue;
             col[e] = perm[cand[q]];
-            v64[e] = -1.0;
             v32[e] = -1.0f;
             ++e;
         }
@@ -1065,10 +1061,13 @@ __global__ void __launch_bounds__(kBlock) rb_fill(int64_t n, int nx, int ny, int
 // (S is positive semidefinite, so a zero diagonal means a zero row); its
 // Jacobi scale is then 1, which leaves that unknown at its initial value.
 __global__ void __launch_bounds__(kBlock) rb_schur_diag(int64_t n, int64_t nr, const int32_t *rp, const int32_t *col,
-                                                        const double *v64, double *d64, float *d32) {
+                                                        const float *v32, double *d64, float *d32) {
     for (int64_t p = nr + (int64_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (int64_t)gridDim.x * kBlock) {
-        double d = v64[rp[p]];
-        for (int32_t e = rp[p] + 1; e < rp[p + 1]; ++e) d -= v64[e] * v64[e] / v64[rp[col[e]]];
+        double d = (double)v32[rp[p]];
+        for (int32_t e = rp[p] + 1; e < rp[p + 1]; ++e) {
+            const double v = (double)v32[e];
+            d -= v * v / (double)v32[rp[col[e]]];
+        }
         if (!(d > 0.0)) d = 1.0;
         d64[p - nr] = d;
         d32[p - nr] = (float)d;
@@ -1125,7 +1124,6 @@ static int rb_build(cfd_csr_t A, bool proj, int gmax, hipStream_t s, RbMatrix **
     if (h == hipSuccess) h = alloc(&M->iperm, n);
     if (h == hipSuccess) h = alloc(&M->rp, n + 1);
     if (h == hipSuccess) h = alloc(&M->col, e + kPad);
-    if (h == hipSuccess) h = alloc(&M->v64, e + kPad);
     if (h == hipSuccess) h = alloc(&M->v32, e + kPad);
     if (h == hipSuccess) h = alloc(&M->d64, n - nr);
     if (h == hipSuccess) h = alloc(&M->d32, n - nr);
@@ -1133,7 +1131,6 @@ static int rb_build(cfd_csr_t A, bool proj, int gmax, hipStream_t s, RbMatrix **
     if (h == hipSuccess) h = hipMemcpy(M->iperm, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
     if (h == hipSuccess) h = hipMemcpy(M->rp, rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice);
     if (h == hipSuccess) h = hipMemsetAsync(M->col + e, 0, sizeof(int32_t) * kPad, s);
-    if (h == hipSuccess) h = hipMemsetAsync(M->v64 + e, 0, sizeof(double) * kPad, s);
     if (h == hipSuccess) h = hipMemsetAsync(M->v32 + e, 0, sizeof(float) * kPad, s);
     if (h != hipSuccess) {
         rb_free(M);
@@ -1141,9 +1138,9 @@ static int rb_build(cfd_csr_t A, bool proj, int gmax, hipStream_t s, RbMatrix **
     }
     const unsigned g = (unsigned)std::min<int64_t>((n + kBlock - 1) / kBlock, 65536);
     hipLaunchKernelGGL(rb_fill, dim3(g), dim3(kBlock), 0, s, n, nx, ny, nz, pin, (const int32_t *)M->perm,
-                       (const int32_t *)M->iperm, (const int32_t *)M->rp, M->col, M->v64, M->v32);
+                       (const int32_t *)M->iperm, (const int32_t *)M->rp, M->col, M->v32);
     hipLaunchKernelGGL(rb_schur_diag, dim3(g), dim3(kBlock), 0, s, n, nr, (const int32_t *)M->rp,
-                       (const int32_t *)M->col, (const double *)M->v64, M->d64, M->d32);
+                       (const int32_t *)M->col, (const float *)M->v32, M->d64, M->d32);
     h = hipGetLastError();
     if (h != hipSuccess) {
         rb_free(M);
@@ -1184,8 +1181,7 @@ static int rb_buffers(RbMatrix *M, bool mixed) {
 struct RbArgs {
     int64_t n, nr, nb;
     const int32_t *rp, *col;
-    const double *v64;
-    const float *v32;
+    const float *v32;       // matrix values (small integers, exact in float32)
     const double *d64;
     const float *d32;
     const int32_t *perm, *iperm;
@@ -1292,11 +1288,11 @@ __global__ void __launch_bounds__(kBlock) rb_rhs(RbArgs a) {
 // yb = D_r^{-1} b_r (for the Schur right-hand side).
 __global__ void __launch_bounds__(kBlock) rb_init_red(RbArgs a) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) double s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
     auto none = [](int64_t) { return 0; };
-    csr_stream_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<float>(a.rp, a.col, a.v32, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.xb[c - a.nr]; });
-        const double bi = a.bp[p], di = s_val[rs];
+        const double bi = a.bp[p], di = (double)s_val[rs];
         a.y64[p] = (bi - acc) / di;
         a.yb[p] = bi / di;
     });
@@ -1307,7 +1303,7 @@ __global__ void __launch_bounds__(kBlock) rb_init_red(RbArgs a) {
 // fresh control state.
 __global__ void __launch_bounds__(kBlock) rb_init_black(RbArgs a, int64_t t) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) double s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
     __shared__ double red[kBlock / 64];
     double gamma = 0.0;
     int fallback = 0;
@@ -1323,13 +1319,13 @@ __global__ void __launch_bounds__(kBlock) rb_init_black(RbArgs a, int64_t t) {
     double rr = 0.0, rp_ = 0.0, rz = 0.0;
     const int64_t pin_p = a.perm[a.pin];
     auto none = [](int64_t) { return 0; };
-    csr_stream_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<float>(a.rp, a.col, a.v32, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double sy = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.y64[c]; });
         const double syb = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.yb[c]; });
         const int64_t k = p - a.nr;
         const double bi = a.bp[p];
         a.bS[k] = bi - syb;
-        const double ri = bi - s_val[rs] * a.xb[k] - sy;
+        const double ri = bi - (double)s_val[rs] * a.xb[k] - sy;
         a.r64[k] = ri;
         rr = fma(ri, ri, rr);
         if (!(a.proj && p == pin_p)) rp_ = fma(ri, ri, rp_);
@@ -1449,8 +1445,8 @@ __device__ inline Decision rb_decide(const RbArgs &a, const CgState &st, double 
 __device__ inline double rb_x_at(const RbArgs &a, int64_t p) {
     if (p >= a.nr) return a.xb[p - a.nr];
     double acc = 0.0;
-    for (int32_t e = a.rp[p] + 1; e < a.rp[p + 1]; ++e) acc = fma(a.v64[e], a.xb[a.col[e] - a.nr], acc);
-    return (a.bp[p] - acc) / a.v64[a.rp[p]];
+    for (int32_t e = a.rp[p] + 1; e < a.rp[p + 1]; ++e) acc = fma((double)a.v32[e], a.xb[a.col[e] - a.nr], acc);
+    return (a.bp[p] - acc) / (double)a.v32[a.rp[p]];
 }
 
 __device__ inline void rb_write_x(const RbArgs &a, bool zero_x) {
@@ -1733,15 +1729,15 @@ __global__ void __launch_bounds__(kBlock) rb_apply(RbArgs a, int64_t t) {
 // Refresh, red sweep (when a refresh is pending): y64 = D_r^{-1} B x_b.
 __global__ void __launch_bounds__(kBlock) rb_f1(RbArgs a, int64_t t) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) double s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
     const RbState st = a.S[t & 1];
     RbState *out = &a.S[(t + 1) & 1];
     if (lead()) *out = st;
     if (st.cg.done || !st.cg.pending) return;
     auto none = [](int64_t) { return 0; };
-    csr_stream_rows<double>(a.rp, a.col, a.v64, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<float>(a.rp, a.col, a.v32, 0, a.nr, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.xb[c - a.nr]; });
-        a.y64[p] = acc / s_val[rs];
+        a.y64[p] = acc / (double)s_val[rs];
     });
 }
 
@@ -1749,7 +1745,7 @@ __global__ void __launch_bounds__(kBlock) rb_f1(RbArgs a, int64_t t) {
 // partial sums of ||r||^2 (all rows, and without the pin row), r^T D_S^{-1} r.
 __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) double s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
     __shared__ double red[kBlock / 64];
     const RbState st = a.S[t & 1];
     RbState *out = &a.S[(t + 1) & 1];
@@ -1760,10 +1756,10 @@ __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     const int64_t pin_p = a.perm[a.pin];
     double rr = 0.0, rp_ = 0.0, rz = 0.0;
     auto none = [](int64_t) { return 0; };
-    csr_stream_rows<double>(a.rp, a.col, a.v64, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
+    csr_stream_rows<float>(a.rp, a.col, a.v32, a.nr, a.n, s_col, s_val, none, [&](int64_t p, int rs, int re, int) {
         const double acc = rb_offdiag<double>(s_col, s_val, rs, re, [&](int32_t c) { return a.y64[c]; });
         const int64_t k = p - a.nr;
-        const double ri = a.bS[k] - s_val[rs] * a.xb[k] + acc;
+        const double ri = a.bS[k] - (double)s_val[rs] * a.xb[k] + acc;
         a.r64[k] = ri;
         rr = fma(ri, ri, rr);
         if (!(a.proj && p == pin_p)) rp_ = fma(ri, ri, rp_);
@@ -1846,7 +1842,6 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     a.nb = nb;
     a.rp = M->rp;
     a.col = M->col;
-    a.v64 = M->v64;
     a.v32 = M->v32;
     a.d64 = M->d64;
     a.d32 = M->d32;
