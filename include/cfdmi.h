@@ -67,8 +67,9 @@ typedef struct cfd_csr *cfd_csr_t;
  * row.  pin >= 0 pins that cell: its row becomes the unit row and its
  * neighbours' entries in that column are dropped (a symmetric positive
  * definite matrix); pin < 0 keeps the singular Neumann matrix (valid for
- * cfd_spmv; cfd_solve rejects it).  Both float64 and float32 value arrays
- * are stored (the values are small integers, exact in both).
+ * cfd_spmv; cfd_solve rejects it).  The values are stored once, in float32
+ * (they are small integers, exact in float32); float64 products of them are
+ * exact, so every float64 kernel reads the same array.
  * Errors: CFD_EINVAL if a dimension is < 1, pin >= n, or nnz >= 2^31.
  * The handle is freed with cfd_csr_destroy.
  */
@@ -79,7 +80,8 @@ int cfd_csr_info(cfd_csr_t A, int64_t *n, int64_t *nnz);
 
 /*
  * Copy the CSR arrays into caller-owned device buffers of n+1, nnz and nnz
- * entries (val receives the float64 values).  Any of the three may be NULL.
+ * entries (val receives the values converted to float64, exactly).  Any of
+ * the three may be NULL.
  */
 int cfd_csr_export(cfd_csr_t A, int32_t *row_ptr, int32_t *col, double *val, void *stream);
 
@@ -87,7 +89,7 @@ void cfd_csr_destroy(cfd_csr_t A);
 
 /*
  * y = A x (Table 1 "spmv") on device vectors of n entries.
- * precision 0: x, y are double*, float64 values.
+ * precision 0: x, y are double*, float64 products and sums.
  * precision 1: x, y are float*,  float32 values, float32 accumulation.
  * x and y must not overlap.
  */

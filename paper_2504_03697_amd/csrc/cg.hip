@@ -147,7 +147,7 @@ static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm, bool 
     if (!A->ws) {
         A->ws = new Workspace();
         A->ws->n = A->n;
-        A->ws->gmax = std::max(grid_spmv(A->n, 4), grid_vec(A->n));
+        A->ws->gmax = std::max(grid_tiles(A->n, 8), grid_vec(A->n));  // no grid has more than 8 per CU
     }
     Workspace *w = A->ws;
     const int64_t n = A->n;

@@ -39,7 +39,7 @@ int device_info(Device *d);
 
 // Grid sizes for the solver's kernels on this device (fixed per device so
 // reductions, which depend on the number of partial sums, are reproducible).
-int grid_spmv(int64_t n, int value_bytes);
+int grid_spmv(int64_t n, bool fp64_vectors);  // the standalone SpMV
 int grid_tiles(int64_t n, int per_cu);  // SpMV-shaped grid with per_cu workgroups per CU
 int grid_vec(int64_t n);
 
@@ -56,8 +56,8 @@ struct cfd_csr {
     int device;
     int32_t *rp = nullptr;    // n+1
     int32_t *col = nullptr;   // nnz + kPad
-    double *val64 = nullptr;  // nnz + kPad
-    float *val32 = nullptr;   // nnz + kPad
+    float *val32 = nullptr;   // nnz + kPad; the values are small integers, exact in float32,
+                              // so the float64 kernels read them too (exact conversion)
     cfd::Workspace *ws = nullptr;
     void *step_ws = nullptr;  // time-step buffers (step.hip)
 };

@@ -47,13 +47,16 @@ static int round_grid(int64_t want, int64_t cap) {
     return (int)std::max<int64_t>(g, 1);
 }
 
+// Workgroups per CU of the standalone SpMV with float64 vectors: measured at
+// 256^3, 245 / 240 / 236 us per product at 6 / 7 / 8.
+constexpr int kSpmv64PerCu = 8;
+
 // Workgroups for the SpMV-shaped kernels: 8 resident workgroups (32 waves)
 // per CU measured best on MI355X at 256^3; at most one per tile.  The grid is
 // the same for every SpMV-shaped kernel of the solver so that their partial
 // sums line up.
-int grid_spmv(int64_t n, int value_bytes) {
-    // float64 slabs need 21.6 KB of LDS per workgroup: 7 fit in 160 KB
-    return grid_tiles(n, value_bytes == 8 ? 7 : 8);
+int grid_spmv(int64_t n, bool fp64_vectors) {
+    return grid_tiles(n, fp64_vectors ? kSpmv64PerCu : 8);
 }
 
 int grid_tiles(int64_t n, int per_cu) {
@@ -111,7 +114,6 @@ __host__ __device__ inline int64_t row_start(int64_t row, int64_t i, int64_t j, 
 __global__ void __launch_bounds__(kBlock) assemble_kernel(int64_t nx, int64_t ny, int64_t nz,
                                                           PinInfo P, int32_t *__restrict__ rp,
                                                           int32_t *__restrict__ col,
-                                                          double *__restrict__ v64,
                                                           float *__restrict__ v32) {
     const int64_t n = nx * ny * nz;
     for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row <= n;
@@ -125,7 +127,6 @@ __global__ void __launch_bounds__(kBlock) assemble_kernel(int64_t nx, int64_t ny
         rp[row] = (int32_t)e;
         if (row == P.pin) {
             col[e] = (int32_t)row;
-            v64[e] = 1.0;
             v32[e] = 1.0f;
             continue;
         }
@@ -138,23 +139,27 @@ __global__ void __launch_bounds__(kBlock) assemble_kernel(int64_t nx, int64_t ny
         for (int q = 0; q < 7; ++q) {
             const int64_t c = cand[q];
             if (c < 0 || c == P.pin) continue;
-            const double a = (c == row) ? (double)deg : -1.0;
             col[e] = (int32_t)c;
-            v64[e] = a;
-            v32[e] = (float)a;
+            v32[e] = (c == row) ? (float)deg : -1.0f;
             ++e;
         }
     }
 }
 
 // Zero the vector over-read padding past nnz so it never holds NaN bits.
-__global__ void pad_kernel(int64_t nnz, int32_t *col, double *v64, float *v32) {
+__global__ void pad_kernel(int64_t nnz, int32_t *col, float *v32) {
     const int t = threadIdx.x;
     if (t < kPad) {
         col[nnz + t] = 0;
-        v64[nnz + t] = 0.0;
         v32[nnz + t] = 0.0f;
     }
+}
+
+// val = the values in float64 (an exact conversion).
+__global__ void __launch_bounds__(kBlock) widen_kernel(int64_t nnz, const float *__restrict__ v32,
+                                                       double *__restrict__ val) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kBlock)
+        val[e] = (double)v32[e];
 }
 
 }  // namespace cfd
@@ -199,7 +204,6 @@ extern "C" int cfd_assemble(const cfd_grid *grid, int64_t pin, void *stream, cfd
     hipError_t e = hipGetDevice(&A->device);
     if (e == hipSuccess) e = hipMalloc(&A->rp, sizeof(int32_t) * (n + 1));
     if (e == hipSuccess) e = hipMalloc(&A->col, sizeof(int32_t) * (nnz + kPad));
-    if (e == hipSuccess) e = hipMalloc(&A->val64, sizeof(double) * (nnz + kPad));
     if (e == hipSuccess) e = hipMalloc(&A->val32, sizeof(float) * (nnz + kPad));
     if (e != hipSuccess) {
         rc = hip_fail(e, "cfd_assemble: hipMalloc");
@@ -209,8 +213,8 @@ extern "C" int cfd_assemble(const cfd_grid *grid, int64_t pin, void *stream, cfd
     hipStream_t s = (hipStream_t)stream;
     const int64_t blocks = std::min<int64_t>((n + 1 + kBlock - 1) / kBlock, 65536);
     hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, nx, ny, nz, P,
-                       A->rp, A->col, A->val64, A->val32);
-    hipLaunchKernelGGL(pad_kernel, dim3(1), dim3(64), 0, s, nnz, A->col, A->val64, A->val32);
+                       A->rp, A->col, A->val32);
+    hipLaunchKernelGGL(pad_kernel, dim3(1), dim3(64), 0, s, nnz, A->col, A->val32);
     e = hipGetLastError();
     if (e != hipSuccess) {
         rc = hip_fail(e, "cfd_assemble: launch");
@@ -234,7 +238,12 @@ extern "C" int cfd_csr_export(cfd_csr_t A, int32_t *row_ptr, int32_t *col, doubl
     if (row_ptr)
         CFD_HIP(hipMemcpyAsync(row_ptr, A->rp, sizeof(int32_t) * (A->n + 1), hipMemcpyDeviceToDevice, s));
     if (col) CFD_HIP(hipMemcpyAsync(col, A->col, sizeof(int32_t) * A->nnz, hipMemcpyDeviceToDevice, s));
-    if (val) CFD_HIP(hipMemcpyAsync(val, A->val64, sizeof(double) * A->nnz, hipMemcpyDeviceToDevice, s));
+    if (val && A->nnz > 0) {
+        const int64_t blocks = std::min<int64_t>((A->nnz + kBlock - 1) / kBlock, 65536);
+        hipLaunchKernelGGL(widen_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, A->nnz,
+                           (const float *)A->val32, val);
+        CFD_HIP(hipGetLastError());
+    }
     return CFD_OK;
 }
 
@@ -244,7 +253,6 @@ extern "C" void cfd_csr_destroy(cfd_csr_t A) {
     if (A->step_ws) step_ws_free(A->step_ws);
     if (A->rp) (void)hipFree(A->rp);
     if (A->col) (void)hipFree(A->col);
-    if (A->val64) (void)hipFree(A->val64);
     if (A->val32) (void)hipFree(A->val32);
     delete A;
 }
@@ -253,22 +261,24 @@ extern "C" void cfd_csr_destroy(cfd_csr_t A) {
 
 namespace cfd {
 
+// y = A x with vectors of type VT; the values are the exact float32 array in
+// both precisions (a float64 product of a converted value is exact).
 template <class VT>
 __global__ void __launch_bounds__(kBlock) spmv_kernel(const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ col,
-                                                      const VT *__restrict__ val, int64_t n,
+                                                      const float *__restrict__ val, int64_t n,
                                                       const VT *__restrict__ x, VT *__restrict__ y) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
-    __shared__ __align__(16) VT s_val[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
     auto xg = [&](int j) { return x[j]; };
     if constexpr (sizeof(VT) == 4) {
-        csr_stream_rows<VT>(rp, col, val, 0, n, s_col, s_val, [](int64_t) { return 0; },
-                            [&](int64_t i, int rs, int re, int) {
-                                store_stream(y + i, row_product_all<VT>(s_col, s_val, rs, re, xg));
-                            });
+        csr_stream_rows<float>(rp, col, val, 0, n, s_col, s_val, [](int64_t) { return 0; },
+                               [&](int64_t i, int rs, int re, int) {
+                                   store_stream(y + i, row_product_all<float>(s_col, s_val, rs, re, xg));
+                               });
     } else {
-        csr_sweep<VT>(rp, col, val, n, s_col, s_val, [&](int64_t i, int rs, int re) {
-            store_stream(y + i, row_product<VT>(s_col, s_val, rs, re, xg));
+        csr_sweep<float>(rp, col, val, n, s_col, s_val, [&](int64_t i, int rs, int re) {
+            store_stream(y + i, row_product<double>(s_col, s_val, rs, re, xg));
         });
     }
 }
@@ -300,9 +310,9 @@ extern "C" int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, 
     if (precision != CFD_PREC_FP64 && precision != CFD_PREC_MIXED)
         return fail(CFD_EINVAL, "cfd_spmv: precision must be 0 (float64) or 1 (float32)");
     hipStream_t s = (hipStream_t)stream;
-    const int G = grid_spmv(A->n, precision == CFD_PREC_FP64 ? 8 : 4);
+    const int G = grid_spmv(A->n, precision == CFD_PREC_FP64);
     if (precision == CFD_PREC_FP64)
-        hipLaunchKernelGGL(spmv_kernel<double>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val64, A->n,
+        hipLaunchKernelGGL(spmv_kernel<double>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val32, A->n,
                            (const double *)x, (double *)y);
     else
         hipLaunchKernelGGL(spmv_kernel<float>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val32, A->n,
