@@ -92,8 +92,9 @@ def measured_traffic(kernel, grid):
 
 
 def spmv_bytes(n, nnz, w):
-    """Plain SpMV y = A x: CSR + x read once + y written once."""
-    return 4 * (n + 1) + nnz * (4 + w) + 2 * w * n
+    """Plain SpMV y = A x with vectors of w bytes: CSR (float32 values in
+    both precisions) + x read once + y written once."""
+    return 4 * (n + 1) + nnz * 8 + 2 * w * n
 
 
 def main():
@@ -209,22 +210,26 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "cg_a32", "bytes_per_launch": a_bytes, "avg_launch_ms": round(a_ms, 5)}
 
-    # isolated plain SpMV (FP32 values and vectors): 100 back-to-back launches,
-    # each bracketed by HIP events on the stream it runs on; median and mean
-    xs = torch.randn(A.n, dtype=torch.float32, device="cuda")
-    ys = torch.empty_like(xs)
-    for _ in range(3):
-        m.spmv(A, xs, ys)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
-    for e0, e1 in ev:
-        e0.record()
-        m.spmv(A, xs, ys)
-        e1.record()
-    torch.cuda.synchronize()
-    spmv_all = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
-    spmv_ms = 0.5 * (spmv_all[49] + spmv_all[50])
-    spmv_mean = sum(spmv_all) / len(spmv_all)
+    # isolated plain SpMV: 100 back-to-back launches, each bracketed by HIP
+    # events on the stream it runs on; median and mean
+    def time_spmv(dtype):
+        xs = torch.randn(A.n, dtype=dtype, device="cuda")
+        ys = torch.empty_like(xs)
+        for _ in range(3):
+            m.spmv(A, xs, ys)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
+        for e0, e1 in ev:
+            e0.record()
+            m.spmv(A, xs, ys)
+            e1.record()
+        torch.cuda.synchronize()
+        t = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        return 0.5 * (t[49] + t[50]), sum(t) / len(t)
+
+    spmv_ms, spmv_mean = time_spmv(torch.float32)
     spmv_gbs = spmv_bytes(A.n, A.nnz, 4) / (spmv_ms * 1e-3) / 1e9
+    spmv64_ms, spmv64_mean = time_spmv(torch.float64)
+    spmv64_gbs = spmv_bytes(A.n, A.nnz, 8) / (spmv64_ms * 1e-3) / 1e9
 
     # plain copy of known size (256 MiB read, 256 MiB written): the reference
     # that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes
@@ -277,6 +282,8 @@ def main():
         "speedup_vs_fp64_projected": round(fp64p["ms_per_solve"] / ms_per_step, 3) if fp64p else None,
         "spmv_fp32_isolated": {"ms": round(spmv_ms, 5), "ms_mean": round(spmv_mean, 5), "launches": 100,
                                "gbs": round(spmv_gbs, 1), "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
+        "spmv_fp64_isolated": {"ms": round(spmv64_ms, 5), "ms_mean": round(spmv64_mean, 5), "launches": 100,
+                               "gbs": round(spmv64_gbs, 1), "frac": round(spmv64_gbs / HBM_PEAK_GBS, 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

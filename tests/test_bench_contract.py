@@ -21,6 +21,7 @@ def test_algorithmic_bytes():
     # the float64 kernel reads the float32 copy of the (integer) matrix values too
     assert bench.a_kernel_bytes(n, nnz, False) == 4 * (n + 1) + 8 * nnz + 48 * n == 1808793556
     assert bench.spmv_bytes(n, nnz, 4) == 4 * (n + 1) + 8 * nnz + 8 * n
+    assert bench.spmv_bytes(n, nnz, 8) == 4 * (n + 1) + 8 * nnz + 16 * n
     assert len(bench.kernel_source_sha()) == 16
 
 
