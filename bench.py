@@ -97,6 +97,16 @@ def spmv_bytes(n, nnz, w):
     return 4 * (n + 1) + nnz * 8 + 2 * w * n
 
 
+def spmv_sym_bytes(n, nnz, w):
+    """y = A x from the symmetric storage: two row-pointer arrays, the
+    diagonal and upper entries (column + float32 value), the lower entries'
+    columns, x read once and y written once (the looked-up lower values are
+    entries already counted in the upper storage)."""
+    nnz_l = (nnz - n) // 2
+    nnz_u = nnz - nnz_l
+    return 8 * (n + 1) + 8 * nnz_u + 4 * nnz_l + 2 * w * n
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,15 +222,15 @@ def main():
 
     # isolated plain SpMV: 100 back-to-back launches, each bracketed by HIP
     # events on the stream it runs on; median and mean
-    def time_spmv(dtype):
+    def time_spmv(dtype, f=m.spmv):
         xs = torch.randn(A.n, dtype=dtype, device="cuda")
         ys = torch.empty_like(xs)
         for _ in range(3):
-            m.spmv(A, xs, ys)
+            f(A, xs, ys)
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(100)]
         for e0, e1 in ev:
             e0.record()
-            m.spmv(A, xs, ys)
+            f(A, xs, ys)
             e1.record()
         torch.cuda.synchronize()
         t = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
@@ -230,6 +240,9 @@ def main():
     spmv_gbs = spmv_bytes(A.n, A.nnz, 4) / (spmv_ms * 1e-3) / 1e9
     spmv64_ms, spmv64_mean = time_spmv(torch.float64)
     spmv64_gbs = spmv_bytes(A.n, A.nnz, 8) / (spmv64_ms * 1e-3) / 1e9
+    # the same product from the symmetric storage (diagonal + upper triangle)
+    sym_ms, sym_mean = time_spmv(torch.float32, m.spmv_sym)
+    sym_gbs = spmv_sym_bytes(A.n, A.nnz, 4) / (sym_ms * 1e-3) / 1e9
 
     # plain copy of known size (256 MiB read, 256 MiB written): the reference
     # that scales rocprofv3's FETCH_SIZE / WRITE_SIZE counters to bytes
@@ -284,6 +297,9 @@ def main():
                                "gbs": round(spmv_gbs, 1), "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
         "spmv_fp64_isolated": {"ms": round(spmv64_ms, 5), "ms_mean": round(spmv64_mean, 5), "launches": 100,
                                "gbs": round(spmv64_gbs, 1), "frac": round(spmv64_gbs / HBM_PEAK_GBS, 4)},
+        "spmv_sym_fp32_isolated": {"ms": round(sym_ms, 5), "ms_mean": round(sym_mean, 5), "launches": 100,
+                                   "bytes": spmv_sym_bytes(A.n, A.nnz, 4), "gbs": round(sym_gbs, 1),
+                                   "time_vs_full_csr": round(sym_ms / spmv_ms, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

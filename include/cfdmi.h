@@ -96,6 +96,20 @@ void cfd_csr_destroy(cfd_csr_t A);
 int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, void *stream);
 
 /*
+ * y = A x from symmetric storage, the layout of Sec. 3.3 (the matrix is
+ * symmetric, so only the diagonal and the upper triangle hold values): a
+ * CSR of the diagonal and upper entries with their values, plus the column
+ * pattern of the lower triangle; the value of lower entry (i, j) is looked
+ * up as entry (j, i) among row j's upper entries.  The storage is built from
+ * the handle's matrix on the first call (kept with the handle; the build
+ * synchronizes the stream once and scans the row counts on the host).
+ * Arguments, precisions and result bits are those of cfd_spmv: each row sums
+ * its terms in ascending column order, as cfd_spmv does.
+ * Errors: CFD_EINVAL (null argument, bad precision), CFD_ENOMEM, CFD_EHIP.
+ */
+int cfd_spmv_sym(cfd_csr_t A, int32_t precision, const void *x, void *y, void *stream);
+
+/*
  * Make a right-hand side consistent with the pinned matrix, in place on the
  * device: subtract its mean (in float64, fixed summation order), then set
  * b[pin] = 0.  For the singular matrix only the mean is removed.

@@ -113,6 +113,18 @@ def spmv(A: Csr, x, y=None, precision=None):
     return y
 
 
+def spmv_sym(A: Csr, x, y=None, precision=None):
+    """y = A x from the symmetric (diagonal + upper triangle) storage
+    (cfd_spmv_sym); same arguments and result bits as spmv()."""
+    torch = _torch()
+    prec = precision if precision is not None else (1 if x.dtype == torch.float32 else 0)
+    dt = torch.float32 if prec == 1 else torch.float64
+    if y is None:
+        y = torch.empty(A.n, dtype=dt, device=x.device)
+    check(load().cfd_spmv_sym(A.handle, prec, _ptr(x, dt, A.n, "x"), _ptr(y, dt, A.n, "y"), _stream()))
+    return y
+
+
 def rhs_prepare(A: Csr, b):
     torch = _torch()
     check(load().cfd_rhs_prepare(A.handle, _ptr(b, torch.float64, A.n, "b"), _stream()))

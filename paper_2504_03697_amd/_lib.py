@@ -70,6 +70,7 @@ def load():
         "cfd_csr_export": (i32, [vp, vp, vp, vp, vp]),
         "cfd_csr_destroy": (None, [vp]),
         "cfd_spmv": (i32, [vp, i32, vp, vp, vp]),
+        "cfd_spmv_sym": (i32, [vp, i32, vp, vp, vp]),
         "cfd_rhs_prepare": (i32, [vp, vp, vp]),
         "cfd_solve": (i32, [vp, vp, vp, dbl, P(CfdSolveOpts), vp, P(CfdSolveInfo), vp]),
         "cfd_step": (i32, [P(CfdState), dbl, dbl, P(CfdSolveOpts), P(CfdSolveInfo), vp]),

@@ -60,6 +60,7 @@ struct cfd_csr {
                               // so the float64 kernels read them too (exact conversion)
     cfd::Workspace *ws = nullptr;
     void *step_ws = nullptr;  // time-step buffers (step.hip)
+    void *sym = nullptr;      // symmetric storage (csr.hip), built on first use
 };
 
 namespace cfd {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 namespace cfd {
 
@@ -247,10 +248,15 @@ extern "C" int cfd_csr_export(cfd_csr_t A, int32_t *row_ptr, int32_t *col, doubl
     return CFD_OK;
 }
 
+namespace cfd {
+static void sym_free(void *p);
+}
+
 extern "C" void cfd_csr_destroy(cfd_csr_t A) {
     if (!A) return;
     if (A->ws) workspace_free(A->ws);
     if (A->step_ws) step_ws_free(A->step_ws);
+    if (A->sym) sym_free(A->sym);
     if (A->rp) (void)hipFree(A->rp);
     if (A->col) (void)hipFree(A->col);
     if (A->val32) (void)hipFree(A->val32);
@@ -317,6 +323,165 @@ extern "C" int cfd_spmv(cfd_csr_t A, int32_t precision, const void *x, void *y, 
     else
         hipLaunchKernelGGL(spmv_kernel<float>, dim3(G), dim3(kBlock), 0, s, A->rp, A->col, A->val32, A->n,
                            (const float *)x, (float *)y);
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+// ---------------------------------------------------------------- symmetric storage
+
+namespace cfd {
+
+// The matrix in the layout of Sec. 3.3: the diagonal and the upper triangle
+// as a CSR with values (diagonal first in each row), and the lower triangle
+// as a column pattern only.  n + 1 row pointers each; kPad zeroed entries
+// past the ends of the slab-loaded arrays.
+struct SymStorage {
+    int64_t nnz_u = 0, nnz_l = 0;
+    int32_t *rp_u = nullptr, *col_u = nullptr, *rp_l = nullptr, *col_l = nullptr;
+    float *val_u = nullptr;
+};
+
+static void sym_free(void *p) {
+    SymStorage *S = (SymStorage *)p;
+    void *pp[] = {S->rp_u, S->col_u, S->rp_l, S->col_l, S->val_u};
+    for (void *q : pp) if (q) (void)hipFree(q);
+    delete S;
+}
+
+// Entries of row i left of the diagonal (the columns ascend in a row).
+__global__ void __launch_bounds__(kBlock) sym_count(int64_t n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col, int32_t *__restrict__ cl) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        int32_t e = rp[i];
+        while (e < rp[i + 1] && col[e] < i) ++e;
+        cl[i] = e - rp[i];
+    }
+}
+
+// Split each row: its lower columns go to col_l at rp_l[i], its diagonal and
+// upper entries to col_u/val_u at rp_u[i] = rp[i] - rp_l[i].
+__global__ void __launch_bounds__(kBlock) sym_fill(int64_t n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col, const float *__restrict__ val,
+                                                   const int32_t *__restrict__ rp_l, int32_t *__restrict__ rp_u,
+                                                   int32_t *__restrict__ col_u, float *__restrict__ val_u,
+                                                   int32_t *__restrict__ col_l) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i <= n; i += (int64_t)gridDim.x * kBlock) {
+        const int32_t l = rp_l[i], u = rp[i] - l;
+        rp_u[i] = u;
+        if (i == n) continue;
+        int32_t k = u;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (col[e] < i) {
+                col_l[l + (e - rp[i])] = col[e];
+            } else {
+                col_u[k] = col[e];
+                val_u[k] = val[e];
+                ++k;
+            }
+        }
+    }
+}
+
+static int sym_build(cfd_csr_t A, hipStream_t s) {
+    if (A->sym) return CFD_OK;
+    const int64_t n = A->n;
+    SymStorage *S = new SymStorage();
+    std::vector<int32_t> cl(n), rpl(n + 1);
+    int32_t *d_cl = nullptr;
+    hipError_t h = hipMalloc(&d_cl, sizeof(int32_t) * std::max<int64_t>(n, 1));
+    const unsigned g = (unsigned)std::min<int64_t>((n + 1 + kBlock - 1) / kBlock, 65536);
+    if (h == hipSuccess) {
+        hipLaunchKernelGGL(sym_count, dim3(g), dim3(kBlock), 0, s, n, (const int32_t *)A->rp,
+                           (const int32_t *)A->col, d_cl);
+        h = hipGetLastError();
+    }
+    if (h == hipSuccess) h = hipMemcpyAsync(cl.data(), d_cl, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
+    if (h == hipSuccess) h = hipStreamSynchronize(s);
+    if (d_cl) (void)hipFree(d_cl);
+    if (h != hipSuccess) {
+        sym_free(S);
+        return hip_fail(h, "cfd_spmv_sym: row counts");
+    }
+    int64_t acc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        rpl[i] = (int32_t)acc;
+        acc += cl[i];
+    }
+    rpl[n] = (int32_t)acc;
+    S->nnz_l = acc;
+    S->nnz_u = A->nnz - acc;
+    if (h == hipSuccess) h = hipMalloc(&S->rp_l, sizeof(int32_t) * (n + 1));
+    if (h == hipSuccess) h = hipMalloc(&S->rp_u, sizeof(int32_t) * (n + 1));
+    if (h == hipSuccess) h = hipMalloc(&S->col_u, sizeof(int32_t) * (S->nnz_u + kPad));
+    if (h == hipSuccess) h = hipMalloc(&S->val_u, sizeof(float) * (S->nnz_u + kPad));
+    if (h == hipSuccess) h = hipMalloc(&S->col_l, sizeof(int32_t) * std::max<int64_t>(S->nnz_l, 1));
+    if (h == hipSuccess) h = hipMemcpyAsync(S->rp_l, rpl.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s);
+    if (h == hipSuccess) h = hipMemsetAsync(S->col_u + S->nnz_u, 0, sizeof(int32_t) * kPad, s);
+    if (h == hipSuccess) h = hipMemsetAsync(S->val_u + S->nnz_u, 0, sizeof(float) * kPad, s);
+    if (h == hipSuccess) {
+        hipLaunchKernelGGL(sym_fill, dim3(g), dim3(kBlock), 0, s, n, (const int32_t *)A->rp, (const int32_t *)A->col,
+                           (const float *)A->val32, (const int32_t *)S->rp_l, S->rp_u, S->col_u, S->val_u, S->col_l);
+        h = hipGetLastError();
+    }
+    // the host copy of the row pointers must outlive the transfer
+    if (h == hipSuccess) h = hipStreamSynchronize(s);
+    if (h != hipSuccess) {
+        sym_free(S);
+        return hip_fail(h, "cfd_spmv_sym: build");
+    }
+    A->sym = S;
+    return CFD_OK;
+}
+
+// y = A x from the symmetric storage.  Per row: the lower terms first, each
+// value found as entry (j, i) among row j's upper entries (after its
+// diagonal; symmetry guarantees it is there, the bound keeps the search in
+// the row otherwise), then the diagonal and upper terms from the staged
+// slab, all in ascending column order with one fused multiply-add each,
+// as the full-CSR product does.
+template <class VT>
+__global__ void __launch_bounds__(kBlock) spmv_sym_kernel(const int32_t *__restrict__ rp_u,
+                                                          const int32_t *__restrict__ col_u,
+                                                          const float *__restrict__ val_u,
+                                                          const int32_t *__restrict__ rp_l,
+                                                          const int32_t *__restrict__ col_l, int64_t n,
+                                                          const VT *__restrict__ x, VT *__restrict__ y) {
+    typedef typename std::conditional<sizeof(VT) == 4, float, double>::type Acc;
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
+    csr_sweep<float>(rp_u, col_u, val_u, n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        Acc acc = Acc(0);
+        for (int32_t e = rp_l[i]; e < rp_l[i + 1]; ++e) {
+            const int32_t j = col_l[e];
+            int32_t k = rp_u[j] + 1;
+            const int32_t kend = rp_u[j + 1];
+            while (k < kend && col_u[k] != (int32_t)i) ++k;
+            if (k < kend) acc = fma(Acc(val_u[k]), Acc(x[j]), acc);
+        }
+        for (int e = rs; e < re; ++e) acc = fma(Acc(s_val[e]), Acc(x[s_col[e]]), acc);
+        store_stream(y + i, (VT)acc);
+    });
+}
+
+}  // namespace cfd
+
+extern "C" int cfd_spmv_sym(cfd_csr_t A, int32_t precision, const void *x, void *y, void *stream) {
+    if (!A || !x || !y) return fail(CFD_EINVAL, "cfd_spmv_sym: null argument");
+    if (precision != CFD_PREC_FP64 && precision != CFD_PREC_MIXED)
+        return fail(CFD_EINVAL, "cfd_spmv_sym: precision must be 0 (float64) or 1 (float32)");
+    hipStream_t s = (hipStream_t)stream;
+    int rc = sym_build(A, s);
+    if (rc != CFD_OK) return rc;
+    const SymStorage *S = (const SymStorage *)A->sym;
+    const int G = grid_spmv(A->n, precision == CFD_PREC_FP64);
+    if (precision == CFD_PREC_FP64)
+        hipLaunchKernelGGL(spmv_sym_kernel<double>, dim3(G), dim3(kBlock), 0, s, (const int32_t *)S->rp_u,
+                           (const int32_t *)S->col_u, (const float *)S->val_u, (const int32_t *)S->rp_l,
+                           (const int32_t *)S->col_l, A->n, (const double *)x, (double *)y);
+    else
+        hipLaunchKernelGGL(spmv_sym_kernel<float>, dim3(G), dim3(kBlock), 0, s, (const int32_t *)S->rp_u,
+                           (const int32_t *)S->col_u, (const float *)S->val_u, (const int32_t *)S->rp_l,
+                           (const int32_t *)S->col_l, A->n, (const float *)x, (float *)y);
     CFD_HIP(hipGetLastError());
     return CFD_OK;
 }

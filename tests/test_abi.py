@@ -66,3 +66,4 @@ def test_host_side_argument_checks():
     info = _lib.CfdSolveInfo()
     assert lib.cfd_solve(None, None, None, 1e-10, None, None, ctypes.byref(info), None) == _lib.CFD_EINVAL
     assert lib.cfd_spmv(None, 0, None, None, None) == _lib.CFD_EINVAL
+    assert lib.cfd_spmv_sym(None, 0, None, None, None) == _lib.CFD_EINVAL

@@ -22,6 +22,10 @@ def test_algorithmic_bytes():
     assert bench.a_kernel_bytes(n, nnz, False) == 4 * (n + 1) + 8 * nnz + 48 * n == 1808793556
     assert bench.spmv_bytes(n, nnz, 4) == 4 * (n + 1) + 8 * nnz + 8 * n
     assert bench.spmv_bytes(n, nnz, 8) == 4 * (n + 1) + 8 * nnz + 16 * n
+    # symmetric storage: every row holds its diagonal, so the off-diagonal
+    # entries split evenly between the triangles
+    nl = (nnz - n) // 2
+    assert bench.spmv_sym_bytes(n, nnz, 4) == 8 * (n + 1) + 8 * (n + nl) + 4 * nl + 8 * n
     assert len(bench.kernel_source_sha()) == 16
 
 

@@ -123,6 +123,53 @@ def test_spmv_full_size_256(lib):
     np.testing.assert_array_equal(y, oracle.spmv(ref, x.astype(np.float64)))
 
 
+# ---------------------------------------------------------------- symmetric storage
+
+SYM_CASES = [((1, 1, 1), 0), ((1, 1, 1), -1), ((2, 1, 1), 1), ((3, 1, 2), 0), ((5, 7, 3), 52),
+             ((16, 16, 16), 0), ((17, 17, 17), -1), ((33, 9, 21), 3000), ((40, 40, 40), 21000)]
+
+
+@pytest.mark.parametrize("dims,pin", SYM_CASES)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_spmv_sym_matches_full_csr(lib, dims, pin, prec):
+    """The symmetric storage (diagonal + upper triangle with values, lower
+    pattern only) gives the full-CSR product's bits: same terms, same
+    ascending order.  Integer vectors also match the oracle exactly, real
+    vectors within the summation bound."""
+    A = lib.assemble(dims, pin)
+    ref = oracle.assemble(dims, pin)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rng = np.random.default_rng(sum(dims) + pin)
+    xi = rng.integers(-8, 9, size=ref.n).astype(np.float64)
+    y = host(lib.spmv_sym(A, dev(xi, dt))).astype(np.float64)
+    np.testing.assert_array_equal(y, oracle.spmv(ref, xi))
+    xr = synth.uniform_rhs(dims, 6)
+    xd = dev(xr, dt)
+    ys = host(lib.spmv_sym(A, xd))
+    yf = host(lib.spmv(A, xd))
+    assert np.array_equal(ys, yf)
+    absA = oracle.Csr(ref.row_ptr, ref.col, np.abs(ref.val), ref.dims, ref.pin)
+    u = 2.0**-53 if prec == "fp64" else 2.0**-24
+    xe = xr if prec == "fp64" else xr.astype(np.float32).astype(np.float64)
+    bound = 2 * 7 * u * oracle.spmv(absA, np.abs(xe)) * 1.01
+    assert np.all(np.abs(ys.astype(np.float64) - oracle.spmv(ref, xe)) <= bound)
+
+
+def test_spmv_sym_full_size_256(lib):
+    """256^3 in the benchmark's launch configuration: integer vectors, the
+    oracle's product exactly; a second call reuses the stored layout."""
+    n = 256
+    A = lib.assemble(n, 0)
+    ref = oracle.assemble(n, 0)
+    rng = np.random.default_rng(4)
+    x = rng.integers(-4, 5, size=ref.n).astype(np.float32)
+    xd = dev(x, torch.float32)
+    y1 = host(lib.spmv_sym(A, xd)).astype(np.float64)
+    np.testing.assert_array_equal(y1, oracle.spmv(ref, x.astype(np.float64)))
+    y2 = host(lib.spmv_sym(A, xd)).astype(np.float64)
+    assert np.array_equal(y1, y2)
+
+
 # ---------------------------------------------------------------- RHS preparation
 
 @pytest.mark.parametrize("dims,pin", [((16, 16, 16), 0), ((17, 13, 11), 100), ((9, 9, 9), -1)])
