@@ -295,9 +295,9 @@ __device__ inline Acc row_product(const int32_t *s_col, const VT *s_val, int rs,
 // pointers it loads stay raw until the commit that consumes the slab.  So
 // nothing between a fetch and that commit waits for the slab, and the
 // row gathers of the current tile overlap it.  It costs registers: the
-// float32 SpMV and the red-black sweeps gain from it (3-4 % at 256^3), the
-// CG kernels with their extra per-row operands, and the float64 SpMV, do
-// not, and keep SlabPipe.
+// float32 SpMV, the red-black sweeps and the float64 CG kernel gain from it
+// (3-4 % at 256^3); the mixed CG kernel (at its 64-register limit) and the
+// float64 SpMV do not, and keep SlabPipe.
 template <class VT>
 struct SlabStream {
     typedef typename std::conditional<sizeof(VT) == 8, f64x2, f32x4>::type VV;
