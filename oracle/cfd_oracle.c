@@ -18,7 +18,7 @@
  *  - Sec. 3.3 "Algorithmic changes": the matrix is symmetric and its
  *    sparsity pattern does not change between steps.
  *
- * Readings where the paper is silent (each also listed in the design doc):
+ * Readings where the paper is silent:
  *  - Matrix: integer 7-point stencil A = -h^2 * Laplacian with homogeneous
  *    Neumann walls: diag = number of in-domain face neighbours, -1 per
  *    neighbour.  The h^2 scale lives in the right-hand side.

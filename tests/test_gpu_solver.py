@@ -1,7 +1,7 @@
 """GPU parity of the matrix, SpMV, right-hand-side preparation and CG solver
 against the FP64 oracle (all calls go through the C ABI).
 
-Tolerances (derived in DESIGN.md, "Parity bars"):
+Tolerances (each derived from the arithmetic it bounds):
 * assembly, SpMV on small-integer vectors: bit-exact (all arithmetic exact);
 * SpMV on real vectors: |y - y_ref| <= 2*gamma_7*(|A||x|) (two different
   rounding sequences of a 7-term dot product, u = 2^-53 or 2^-24);
