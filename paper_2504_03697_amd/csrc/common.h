@@ -120,8 +120,18 @@ __device__ inline double block_sum(double v, double *red) {
 // (thread t sums entries t, t+256, ... serially, then block_sum).  Every
 // block of the calling kernel obtains the same bits.
 __device__ inline double reduce_partials(const double *part, int count, double *red) {
+    // eight loads in flight, then the adds in the same order as one at a time
+    // (every kernel starts with this reduction: 0.6 % off the mixed SpMV kernel)
     double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += kBlock) s += part[i];
+    int i = threadIdx.x;
+    for (; i + 7 * kBlock < count; i += 8 * kBlock) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = part[i + k * kBlock];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; i < count; i += kBlock) s += part[i];
     return block_sum(s, red);
 }
 
