@@ -49,3 +49,16 @@ def test_s_product_bytes_match_the_matrix():
         assert bench.s_product_bytes(N) == want
         want64 = (4 * (nr + 1) + 8 * nnz_r + 16 * nb + 8 * nr + 8 * nb) + (4 * (nb + 1) + 8 * nnz_b + 8 * nb + 8 * nr + 8 * nb)
         assert bench.s_product_bytes(N, 8) == want64
+
+
+def test_committed_profile_matches_the_kernel_sources():
+    """The HBM traffic the bench reports comes from a committed PMC summary
+    keyed by a hash of the CG kernel sources: one must exist for the sources
+    as they are, within a few percent of the kernel's algorithmic bytes."""
+    sys.path.insert(0, ROOT)
+    import bench
+    n = 256
+    t = bench.measured_traffic("cg_a32", n)
+    assert t is not None, "re-profile cg_a32 (profiles/cg_a32_poisson_256.md) for the current sources"
+    alg = bench.a_kernel_bytes(n**3, 7 * n**3 - 6 * n**2 - 6, True)
+    assert alg <= t <= 1.2 * alg
