@@ -431,6 +431,14 @@ def test_solve_512_largest_grid(lib):
         assert x[0] == 0.0
         print(f"512^3 {list(kw)}: {info['iters']} iterations, {info['seconds']:.2f} s")
         del x
+    # the products at this size, on integer vectors: the oracle's bits, from
+    # the full CSR in both precisions and from the symmetric storage
+    xi = np.random.default_rng(7).integers(-4, 5, size=ref.n).astype(np.float32)
+    y_ref = oracle.spmv(ref, xi.astype(np.float64))
+    x32 = dev(xi, torch.float32)
+    assert np.array_equal(host(lib.spmv(A, x32)).astype(np.float64), y_ref)
+    assert np.array_equal(host(lib.spmv_sym(A, x32)).astype(np.float64), y_ref)
+    assert np.array_equal(host(lib.spmv(A, dev(xi.astype(np.float64)))), y_ref)
 
 
 def test_solve_edge_cases(lib):
