@@ -179,3 +179,63 @@ def test_wall_ghosts_by_diffusion(comp):
     interior = (own >= 1) & (own <= n - 1)
     np.testing.assert_allclose(out[interior], expect[interior], rtol=0, atol=1e-15)
     assert not out[~interior].any()
+
+
+def _face_coords(dims, h, comp):
+    """Physical coordinates of every face of one component, in storage order
+    (x fastest): u faces sit at (i h, (j+1/2) h, (k+1/2) h), v faces at
+    ((i+1/2) h, j h, (k+1/2) h), w faces at ((i+1/2) h, (j+1/2) h, k h)."""
+    nx, ny, nz = dims
+    fx, fy, fz = nx + (comp == 0), ny + (comp == 1), nz + (comp == 2)
+    k, j, i = np.meshgrid(np.arange(fz), np.arange(fy), np.arange(fx), indexing="ij")
+    x = (i + (0.0 if comp == 0 else 0.5)) * h
+    y = (j + (0.0 if comp == 1 else 0.5)) * h
+    z = (k + (0.0 if comp == 2 else 0.5)) * h
+    return (i, j, k), (x.reshape(-1), y.reshape(-1), z.reshape(-1))
+
+
+@pytest.mark.parametrize("dims", [(12, 10, 14), (9, 13, 11)])
+def test_advection_of_linear_fields_is_exact(dims):
+    """Semi-Lagrangian advection (Sec. 3.1) of a velocity whose three
+    components are affine functions of position.  Trilinear interpolation
+    reproduces an affine function exactly, so on every face whose sampling
+    stencils stay among real faces, the advected value must equal the
+    component's affine function at the departure point X - dt V(X), with V(X)
+    the affine velocity at the face position X.  Every component depends on
+    all three coordinates, so a wrong half-cell offset when one component is
+    sampled at another component's faces, or a wrong weight in any
+    direction, moves the departure point and fails this check."""
+    nx, ny, nz = dims
+    h = 1.0 / max(dims)
+    # u = a0 + a.(x, y, z), v = b0 + b.(x, y, z), w = c0 + c.(x, y, z)
+    coef = np.array([[0.30, 0.20, -0.50, 0.40],
+                     [-0.20, 0.60, 0.10, -0.30],
+                     [0.25, -0.40, 0.35, 0.15]])
+
+    def field(comp, x, y, z):
+        c = coef[comp]
+        return c[0] + c[1] * x + c[2] * y + c[3] * z
+
+    # |V| <= 0.3 + 0.2 + 0.5 + 0.4 < 1.5 on the unit box; dt keeps every
+    # departure point within 0.4 h of its face
+    dt = 0.4 * h / 1.5
+    comps = [_face_coords(dims, h, c) for c in range(3)]
+    f = [field(c, *comps[c][1]) for c in range(3)]
+    out = oracle.advect(dims, h, 0.0, dt, *f)
+    checked = 0
+    for c in range(3):
+        (i, j, k), (x, y, z) = comps[c]
+        i, j, k = i.reshape(-1), j.reshape(-1), k.reshape(-1)
+        V = [field(d, x, y, z) for d in range(3)]
+        xd, yd, zd = x - dt * V[0], y - dt * V[1], z - dt * V[2]
+        expect = field(c, xd, yd, zd)
+        # two faces of margin from every wall: all sampling corners (at X and
+        # at the departure point, for all three components) are real faces
+        m = ((i >= 2) & (i <= nx + (c == 0) - 3) & (j >= 2) & (j <= ny + (c == 1) - 3)
+             & (k >= 2) & (k <= nz + (c == 2) - 3))
+        scale = np.abs(expect[m]).max()
+        np.testing.assert_allclose(out[c][m], expect[m], rtol=0, atol=1e-14 * scale)
+        # the check is not vacuous: the departure moved every value
+        assert np.all(np.abs(f[c][m] - expect[m]) > 1e-6)
+        checked += int(m.sum())
+    assert checked > 500
