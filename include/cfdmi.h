@@ -177,7 +177,11 @@ typedef struct cfd_solve_opts {
                             red-black copy of the matrix (float32 values,
                             exact) is built on the first such solve of
                             each formulation and kept with the handle.      */
-    int32_t reserved_;
+    int32_t debug_breakdown_at; /* testing only; 0 in normal use.  k > 0: the
+                            k-th iteration's step length is rejected as if
+                            p^T A p <= 0, so the solve ends with
+                            CFD_EBREAKDOWN and the iterate of k-1 updates
+                            (the error path, exercised on demand).        */
 } cfd_solve_opts;
 
 typedef struct cfd_solve_info {
@@ -197,7 +201,8 @@ typedef struct cfd_solve_info {
 /*
  * Solve A x = b for the pinned matrix A to ||b - A x|| <= tol * ||b||
  * (float64 true residual), starting from x0 (device, may be NULL = zero
- * guess, may alias x).  b, x0, x: device double[n].  On CFD_ENOCONV,
+ * guess, may alias x).  b, x0, x: device double[n]; x must not overlap b,
+ * and x0 must either be x itself or not overlap it (CFD_EINVAL).  On CFD_ENOCONV,
  * CFD_EBREAKDOWN and CFD_ENONFINITE, x holds the last iterate and info is
  * filled.  b = 0 returns x = 0 after 0 iterations.  b must be consistent
  * (see cfd_rhs_prepare).  Synchronises the stream before returning.

@@ -132,21 +132,22 @@ def rhs_prepare(A: Csr, b):
 
 
 def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned",
-               precond="none"):
+               precond="none", debug_breakdown_at=0):
     """cfd_solve_opts; precond "dic" = the DIC preconditioner in red-black order."""
     return CfdSolveOpts(PREC[precision] if isinstance(precision, str) else int(precision), int(max_iters),
                         float(ru_delta), net.handle if net is not None else None, int(chunk), int(bool(timing)),
                         FORM[formulation] if isinstance(formulation, str) else int(formulation), 0,
-                        PRECOND[precond] if isinstance(precond, str) else int(precond), 0)
+                        PRECOND[precond] if isinstance(precond, str) else int(precond), int(debug_breakdown_at))
 
 
 def solve(A: Csr, b, x0=None, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0,
-          chunk=0, timing=False, x=None, raise_on_error=True, formulation="pinned", precond="none"):
+          chunk=0, timing=False, x=None, raise_on_error=True, formulation="pinned", precond="none",
+          debug_breakdown_at=0):
     """Solve A x = b on the device.  Returns (x, info dict)."""
     torch = _torch()
     if x is None:
         x = torch.empty(A.n, dtype=torch.float64, device=b.device)
-    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing, formulation, precond)
+    opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing, formulation, precond, debug_breakdown_at)
     info = CfdSolveInfo()
     rc = load().cfd_solve(A.handle, _ptr(b, torch.float64, A.n, "b"), _ptr(x0, torch.float64, A.n, "x0"),
                           float(tol), ctypes.byref(opts), _ptr(x, torch.float64, A.n, "x"),

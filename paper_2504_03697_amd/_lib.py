@@ -22,7 +22,7 @@ class CfdSolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("ru_delta", ctypes.c_double),
                 ("net", ctypes.c_void_p), ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("formulation", ctypes.c_int32), ("step_guess", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("debug_breakdown_at", ctypes.c_int32)]
 
 
 class CfdSolveInfo(ctypes.Structure):

@@ -82,6 +82,7 @@ struct SolveArgs {
     const float *v32;       // matrix values: small integers, exact in float32
     double tol, ru_delta;
     int32_t max_iters;
+    int32_t break_at;       // testing: iteration whose step length is treated as a breakdown (-1: none)
     int32_t Ga, Gb, Gf;
     int64_t pin;
     int32_t proj;           // 1: CG on the consistent Neumann system, shifted at exit
@@ -550,12 +551,16 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
     }
     const double pq = reduce_partials(a.partA, a.Ga, red);
     const double alpha = st.rho / pq;
-    if (!(pq > 0.0) || !std::isfinite(alpha)) {
+    if (!(pq > 0.0) || !std::isfinite(alpha) || st.iters == a.break_at) {
         if (lead()) {
             CgState ns = st;
             ns.pending = 1;
             ns.reason = R_BREAKDOWN;
             ns.alpha = 0.0;
+            // mixed: this iteration's direction is not queued, so the newest
+            // queued update is the one before it; point pcur back at it
+            // (pend_slot() counts the queue back from pcur)
+            if (MIXED) ns.pcur = (st.pcur - 1 + kRing) % kRing;
             *out = ns;
         }
         return;
@@ -783,6 +788,10 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
                       double *x, cfd_solve_info *info, hipStream_t s) {
     cfd_solve_opts opts{};
     if (o) opts = *o;
+    // x is written while b (and x0, unless it is x itself) are still read
+    auto overlap = [&](const double *u, const double *v) { return u < v + A->n && v < u + A->n; };
+    if (overlap(x, b)) return fail(CFD_EINVAL, "cfd_solve: x must not overlap b");
+    if (x0 && x0 != x && overlap(x, x0)) return fail(CFD_EINVAL, "cfd_solve: x0 must be x itself or not overlap it");
     const bool mixed = opts.precision == CFD_PREC_MIXED;
     if (opts.precision != CFD_PREC_FP64 && !mixed) return fail(CFD_EINVAL, "cfd_solve: unknown precision");
     if (A->pin < 0) return fail(CFD_EINVAL, "cfd_solve: the singular Neumann matrix needs a pinned cell");
@@ -809,6 +818,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.tol = tol;
     a.ru_delta = delta;
     a.max_iters = max_iters;
+    a.break_at = opts.debug_breakdown_at > 0 ? opts.debug_breakdown_at : -1;
     const Grids &gr = solver_grids();
     a.Ga = grid_tiles(A->n, mixed ? gr.a32 : gr.a64);
     a.Gb = grid_vec(A->n);
@@ -1189,6 +1199,7 @@ struct RbArgs {
     const int32_t *perm, *iperm;
     double tol, ru_delta;
     int32_t max_iters;
+    int32_t break_at;       // testing: as in SolveArgs
     int32_t G1, G2, Gv;     // red and black sweeps of the iteration, black vector kernels
     int32_t Gf1, Gf2;       // red and black sweeps of the initial residual and the refresh
     int32_t Gw, Gs;         // partial counts of the warm-start and right-hand-side sums
@@ -1606,11 +1617,14 @@ __global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
     }
     const double pq = reduce_partials(a.partA, a.G2, red);
     const double alpha = st.cg.rho / pq;
-    if (!(pq > 0.0) || !std::isfinite(alpha)) {
+    if (!(pq > 0.0) || !std::isfinite(alpha) || st.cg.iters == a.break_at) {
         if (lead()) {
             RbState ns = st;
             ns.cg.pending = 1;
             ns.cg.reason = R_BREAKDOWN;
+            // mixed: as in cg_b, the newest queued update is the previous
+            // direction, so rb_apply must count the queue back from it
+            if (MIXED) ns.cg.pcur = (st.cg.pcur - 1 + kRing) % kRing;
             *out = ns;
         }
         return;
@@ -1856,6 +1870,7 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     a.tol = tol;
     a.ru_delta = delta;
     a.max_iters = max_iters;
+    a.break_at = opts.debug_breakdown_at > 0 ? opts.debug_breakdown_at : -1;
     // the red sweep writes no partial sums, so its two instances get grids of their own
     static const int k1g_per_cu[2] = {resident_per_cu(rb_k1<false, true>), resident_per_cu(rb_k1<true, true>)};
     static const int k1_per_cu[2] = {resident_per_cu(rb_k1<false, false>), resident_per_cu(rb_k1<true, false>)};

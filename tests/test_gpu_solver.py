@@ -324,6 +324,53 @@ def test_config_128_100_standalone_solves(lib):
     print(f"128^3, 100 solves: iterations {min(iters)}..{max(iters)}, mean {np.mean(iters):.1f}")
 
 
+
+@pytest.mark.parametrize("precision,precond", [("fp64", "none"), ("mixed", "none"), ("fp64", "dic"),
+                                               ("mixed", "dic")])
+@pytest.mark.parametrize("k", [37, 38, 39, 40])
+def test_breakdown_returns_last_iterate(lib, precision, precond, k):
+    """A breakdown at iteration k (p^T A p <= 0, forced through the testing
+    option debug_breakdown_at) ends the solve with CFD_EBREAKDOWN and x = the
+    iterate of k-1 updates: the same bits as a solve capped at k-1 iterations
+    (CFD_ENOCONV).  k = 37..40 puts the breakdown at every position of the
+    mixed path's four-deep queue of x updates."""
+    from paper_2504_03697_amd._lib import CFD_EBREAKDOWN, CFD_ENOCONV
+    dims = (24, 13, 31)
+    b = make_rhs(dims, "uniform", 3)
+    A = lib.assemble(dims, 0)
+    bd = dev(b)
+    xb, ib = lib.solve(A, bd, tol=1e-10, precision=precision, precond=precond, debug_breakdown_at=k,
+                       raise_on_error=False)
+    xc, ic = lib.solve(A, bd, tol=1e-10, precision=precision, precond=precond, max_iters=k - 1,
+                       raise_on_error=False)
+    assert ib["rc"] == CFD_EBREAKDOWN and ib["status"] == CFD_EBREAKDOWN and ib["iters"] == k
+    assert ic["rc"] == CFD_ENOCONV and ic["iters"] == k - 1
+    xb, xc = host(xb), host(xc)
+    assert np.array_equal(xb, xc)
+    # and that iterate is what the reported residual belongs to
+    ref = oracle.assemble(dims, 0)
+    rr = true_relres(ref, b, xb)
+    assert abs(rr - ib["rel_residual"]) <= 1e-6 * rr
+
+
+def test_solve_rejects_x_overlapping_b(lib):
+    """x is written while b is still read: x = b, or any overlap, is CFD_EINVAL
+    (and so is an x0 that overlaps x without being x)."""
+    dims = (8, 8, 8)
+    A = lib.assemble(dims, 0)
+    b = dev(make_rhs(dims, "uniform", 0))
+    with pytest.raises(lib.CfdError):
+        lib.solve(A, b, x=b)
+    buf = torch.zeros(2 * A.n, dtype=torch.float64, device="cuda")
+    buf[: A.n] = b
+    with pytest.raises(lib.CfdError):
+        lib.solve(A, buf[: A.n], x=buf[5: 5 + A.n])
+    with pytest.raises(lib.CfdError):
+        lib.solve(A, b, x0=buf[: A.n], x=buf[3: 3 + A.n])
+    x, info = lib.solve(A, b, x0=buf[: A.n], x=buf[: A.n])  # x0 aliasing x is allowed
+    assert info["status"] == 0
+
+
 _TRUTH = {}
 
 
