@@ -22,7 +22,8 @@ class CfdSolveOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("ru_delta", ctypes.c_double),
                 ("net", ctypes.c_void_p), ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("formulation", ctypes.c_int32), ("step_guess", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("debug_breakdown_at", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("debug_breakdown_at", ctypes.c_int32),
+                ("stop_margin", ctypes.c_double)]
 
 
 class CfdSolveInfo(ctypes.Structure):

@@ -201,19 +201,9 @@ def make_rhs(dims, kind, seed):
     return oracle.rhs_prepare(b, 0)
 
 
-MIXED_WHITE_NOISE = pytest.mark.xfail(
-    reason="pinned formulation, mixed precision, white-noise right-hand side: a 1e-10 residual leaves "
-           "error in the lowest modes (the pinned cell's isolated eigenvalue ~1.45/N^3 and the smooth modes, "
-           "where the float32 SpMV cancels); 2.6e-9..5e-9 measured on this grid against the 1e-9 bar. The "
-           "projected formulation meets the bar here (7.8e-10); smoothed and cavity right-hand sides meet it "
-           "with a wide margin", strict=False)
-
-
 @pytest.mark.parametrize("dims,kind,seed", CASES)
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_solve_parity(lib, dims, kind, seed, precision, request):
-    if precision == "mixed" and kind == "uniform" and dims == (24, 13, 31):
-        request.applymarker(MIXED_WHITE_NOISE)
+def test_solve_parity(lib, dims, kind, seed, precision):
     tol = 1e-10
     ref = oracle.assemble(dims, 0)
     b = make_rhs(dims, kind, seed)
@@ -369,6 +359,82 @@ def test_solve_rejects_x_overlapping_b(lib):
         lib.solve(A, b, x0=buf[: A.n], x=buf[3: 3 + A.n])
     x, info = lib.solve(A, b, x0=buf[: A.n], x=buf[: A.n])  # x0 aliasing x is allowed
     assert info["status"] == 0
+
+
+
+def _white_truth(n, seed):
+    key = ("white", n, seed)
+    if key not in _TRUTH:
+        ref = oracle.assemble(n, 0)
+        b = make_rhs((n, n, n), "uniform", seed)
+        _TRUTH[key] = (ref, b, oracle.cg(ref, b, tol=1e-12)[0])
+    return _TRUTH[key]
+
+
+@pytest.mark.parametrize("n,seed", [(96, 0), (96, 1), (128, 1), (128, 2)])
+@pytest.mark.parametrize("form", ["pinned", "projected"])
+@pytest.mark.parametrize("precond", ["none", "dic"])
+def test_mixed_white_noise_pressure_error(lib, n, seed, form, precond):
+    """Mixed precision on white-noise (uniform[-1,1]) right-hand sides, whose
+    lowest modes hold the least of b, so float32 rounding noise there weighs
+    most: with the default stopping margin (true residual <= 0.05 tol) the
+    pressure is within 1e-9 of an oracle solve at 1e-12 (relative L2, mean
+    removed) and the residual meets tol.  At a residual of 1e-10 itself these
+    right-hand sides measured 1.8e-9..3e-8 (128^3)."""
+    ref, b, truth = _white_truth(n, seed)
+    A = lib.assemble(n, 0)
+    x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation=form, precond=precond)
+    x = host(x)
+    assert info["status"] == 0 and info["rel_residual"] <= 0.05e-10 * 1.0001
+    assert true_relres(ref, b, x) <= 0.05e-10 + relres_rounding(ref, b, x)
+    e = mean_removed_err(x, truth)
+    print(f"white {n}^3 seed {seed} {form} {precond}: {info['iters']} iterations, error {e:.2e}")
+    assert e <= 1e-9
+
+
+def test_stop_margin_option(lib):
+    """stop_margin sets the residual the solve runs to (tol * margin); 1
+    gives the residual-only stop, more iterations follow a smaller margin,
+    and the float64 default is 1."""
+    n = 32
+    A = lib.assemble(n, 0)
+    ref = oracle.assemble(n, 0)
+    b = make_rhs((n, n, n), "uniform", 5)
+    bd = dev(b)
+    its = []
+    for m in (1.0, 0.1, 0.01):
+        x, info = lib.solve(A, bd, tol=1e-10, precision="mixed", stop_margin=m)
+        assert info["rel_residual"] <= 1e-10 * m
+        assert true_relres(ref, b, host(x)) <= 1e-10 * m + relres_rounding(ref, b, host(x))
+        its.append(info["iters"])
+    assert its[0] < its[1] < its[2]
+    x, info = lib.solve(A, bd, tol=1e-10, precision="mixed")
+    assert info["iters"] == lib.solve(A, bd, tol=1e-10, precision="mixed", stop_margin=0.05)[1]["iters"]
+    it64 = lib.solve(A, bd, tol=1e-10, precision="fp64")[1]["iters"]
+    assert it64 == lib.solve(A, bd, tol=1e-10, precision="fp64", stop_margin=1.0)[1]["iters"]
+
+
+def test_mixed_cavity_rhs_pressure_error(lib):
+    """A cavity right-hand side (64^3, Re = 1000, after 15 oracle time steps
+    from rest), built from the oracle's own step pieces (advection, viscosity,
+    divergence, consistency): the mixed solve, both formulations, is within
+    1e-9 of an oracle solve at 1e-12."""
+    n, dt, nu = 64, 0.005, 1e-3
+    S = oracle.State(n, nu=nu, lid=1.0)
+    for _ in range(15):
+        assert oracle.step(S, dt, tol=1e-10)[2] == oracle.OK
+    ua, va, wa = oracle.advect(n, S.h, 1.0, dt, S.u, S.v, S.w)
+    u, v, w = oracle.diffuse(n, S.h, 1.0, dt, nu, ua, va, wa)
+    b = oracle.rhs_prepare(-(S.rho * S.h / dt) * oracle.divergence(n, u, v, w), 0)
+    ref = oracle.assemble(n, 0)
+    truth = oracle.cg(ref, b, tol=1e-12)[0]
+    A = lib.assemble(n, 0)
+    for form in ("pinned", "projected"):
+        x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation=form)
+        x = host(x)
+        assert info["status"] == 0
+        assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
+        assert mean_removed_err(x, truth) <= 1e-9, form
 
 
 _TRUTH = {}
