@@ -116,6 +116,21 @@ int cfd_spmv_sym(cfd_csr_t A, int32_t precision, const void *x, void *y, void *s
  */
 int cfd_rhs_prepare(cfd_csr_t A, double *b, void *stream);
 
+/*
+ * cfd_rhs_prepare for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and result bits, with the partial sums in a fixed 8 KiB
+ * device array of the library instead of the matrix handle's workspace, so
+ * the call allocates nothing (cfd_rhs_prepare allocates that workspace on
+ * its first call).  Limit: the reduction grid of n must fit the 1024 partial
+ * sums the array holds, true for every n on a device with at most 256 compute
+ * units; otherwise CFD_EINVAL.  Call it with A's device current (else
+ * CFD_EINVAL).  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on the same GPU (concurrent streams or threads) race and must not
+ * be issued.
+ */
+int cfd_rhs_prepare_noalloc(cfd_csr_t A, double *b, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Solver (Sec. 3.1: conjugate gradients, unpreconditioned or with DIC) */
 /* ------------------------------------------------------------------ */

@@ -131,6 +131,14 @@ def rhs_prepare(A: Csr, b):
     return b
 
 
+def rhs_prepare_noalloc(A: Csr, b):
+    """cfd_rhs_prepare_noalloc: rhs_prepare with the library's fixed scratch
+    array (no device allocation)."""
+    torch = _torch()
+    check(load().cfd_rhs_prepare_noalloc(A.handle, _ptr(b, torch.float64, A.n, "b"), _stream()))
+    return b
+
+
 def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned",
                precond="none", debug_breakdown_at=0, stop_margin=0.0):
     """cfd_solve_opts; precond "dic" = the DIC preconditioner in red-black order;

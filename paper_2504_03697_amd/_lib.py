@@ -73,6 +73,7 @@ def load():
         "cfd_spmv": (i32, [vp, i32, vp, vp, vp]),
         "cfd_spmv_sym": (i32, [vp, i32, vp, vp, vp]),
         "cfd_rhs_prepare": (i32, [vp, vp, vp]),
+        "cfd_rhs_prepare_noalloc": (i32, [vp, vp, vp]),
         "cfd_solve": (i32, [vp, vp, vp, dbl, P(CfdSolveOpts), vp, P(CfdSolveInfo), vp]),
         "cfd_step": (i32, [P(CfdState), dbl, dbl, P(CfdSolveOpts), P(CfdSolveInfo), vp]),
         "cfd_net_create": (i32, [i32, i32, vp, P(vp)]),

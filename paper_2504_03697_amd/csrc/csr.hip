@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace cfd {
@@ -496,6 +497,61 @@ extern "C" int cfd_rhs_prepare(cfd_csr_t A, double *b, void *stream) {
     if (!part) return CFD_ENOMEM;
     hipStream_t s = (hipStream_t)stream;
     const int G = grid_vec(A->n);
+    hipLaunchKernelGGL(sum_kernel, dim3(G), dim3(kBlock), 0, s, (const double *)b, A->n, part);
+    hipLaunchKernelGGL(center_kernel, dim3(G), dim3(kBlock), 0, s, b, A->n, A->pin, (const double *)part, G);
+    CFD_HIP(hipGetLastError());
+    return CFD_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free variant
+
+namespace cfd {
+
+// Partial sums of cfd_rhs_prepare_noalloc: a fixed device array instead of
+// the matrix handle's workspace.  Every GPU the library runs on holds its own
+// copy until the process ends; calls on one GPU share it (the last call's
+// partial sums stay there), so calls that overlap on one GPU race.
+constexpr int kNoAllocParts = 1024;  // 8 KiB
+static __device__ __align__(256) double scratch[kNoAllocParts];
+
+constexpr int kMaxDevices = 64;
+static double *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device, looked up once per
+// device (host code must not pass the symbol itself to a kernel).
+static int scratch_address(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(CFD_EINVAL, "cfd_rhs_prepare_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                     "cfd_rhs_prepare_noalloc: hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return CFD_OK;
+}
+
+}  // namespace cfd
+
+extern "C" int cfd_rhs_prepare_noalloc(cfd_csr_t A, double *b, void *stream) {
+    if (!A || !b) return fail(CFD_EINVAL, "cfd_rhs_prepare_noalloc: null argument");
+    int dev = -1;
+    CFD_HIP(hipGetDevice(&dev));
+    if (dev != A->device)
+        return fail(CFD_EINVAL, "cfd_rhs_prepare_noalloc: call with the matrix's device current");
+    // the same grid, kernels and summation order as cfd_rhs_prepare
+    const int G = grid_vec(A->n);
+    if (G > kNoAllocParts)
+        return fail(CFD_EINVAL, "cfd_rhs_prepare_noalloc: needs " + std::to_string(G) +
+                                    " partial sums, more than the fixed scratch holds (" +
+                                    std::to_string(kNoAllocParts) + ")");
+    double *part = nullptr;
+    int rc = scratch_address(dev, &part);
+    if (rc != CFD_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(sum_kernel, dim3(G), dim3(kBlock), 0, s, (const double *)b, A->n, part);
     hipLaunchKernelGGL(center_kernel, dim3(G), dim3(kBlock), 0, s, b, A->n, A->pin, (const double *)part, G);
     CFD_HIP(hipGetLastError());
