@@ -141,6 +141,7 @@ enum { CFD_PREC_FP64 = 0, CFD_PREC_MIXED = 1 };
 enum { CFD_FORM_PINNED = 0, CFD_FORM_PROJECTED = 1 };
 enum { CFD_GUESS_ZERO = 0, CFD_GUESS_PREVIOUS = 1 };
 enum { CFD_PRECOND_NONE = 0, CFD_PRECOND_DIC_RB = 1 };
+enum { CFD_DRIVER_AUTO = 0, CFD_DRIVER_STEPS = 1, CFD_DRIVER_PERSISTENT = 2 };
 
 typedef struct cfd_solve_opts {
     int32_t precision;   /* CFD_PREC_FP64: CG in float64 throughout (the
@@ -206,6 +207,21 @@ typedef struct cfd_solve_opts {
                             noise and cavity right-hand sides the mixed path
                             measured 1e-9..3e-8 relative pressure error at a
                             1e-10 residual, <= 3e-10 at 0.05 * 1e-10.      */
+    int32_t driver;      /* unpreconditioned solves only (the DIC path always
+                            launches per step):
+                            CFD_DRIVER_STEPS: one kernel launch per step
+                            (SpMV, vector update, refresh), the host
+                            polling the device state every `chunk`
+                            iterations.  CFD_DRIVER_PERSISTENT: one
+                            cooperative launch runs every iteration, its
+                            steps separated by grid barriers (CFD_EINVAL if
+                            the device cannot launch cooperatively).
+                            CFD_DRIVER_AUTO (0): persistent for grids of at
+                            most 24^3 cells, where launch overhead sets the
+                            iteration time, else one launch per step.      */
+    int32_t barrier_spins; /* persistent driver: polls before a grid barrier
+                            wait gives up (<= 0: about 4M, ~0.3 s); the
+                            solve then ends with CFD_EHIP.  Testing only.  */
 } cfd_solve_opts;
 
 typedef struct cfd_solve_info {

@@ -139,26 +139,32 @@ def rhs_prepare_noalloc(A: Csr, b):
     return b
 
 
+DRIVER = {"auto": 0, "steps": 1, "persistent": 2}
+
+
 def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned",
-               precond="none", debug_breakdown_at=0, stop_margin=0.0):
+               precond="none", debug_breakdown_at=0, stop_margin=0.0, driver="auto", barrier_spins=0):
     """cfd_solve_opts; precond "dic" = the DIC preconditioner in red-black order;
-    stop_margin <= 0: the library's default (0.05 mixed, 1 float64)."""
+    stop_margin <= 0: the library's default (0.05 mixed, 1 float64); driver
+    "auto", "steps" (one launch per step) or "persistent" (one cooperative
+    launch)."""
     return CfdSolveOpts(PREC[precision] if isinstance(precision, str) else int(precision), int(max_iters),
                         float(ru_delta), net.handle if net is not None else None, int(chunk), int(bool(timing)),
                         FORM[formulation] if isinstance(formulation, str) else int(formulation), 0,
                         PRECOND[precond] if isinstance(precond, str) else int(precond), int(debug_breakdown_at),
-                        float(stop_margin))
+                        float(stop_margin), DRIVER[driver] if isinstance(driver, str) else int(driver),
+                        int(barrier_spins))
 
 
 def solve(A: Csr, b, x0=None, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0,
           chunk=0, timing=False, x=None, raise_on_error=True, formulation="pinned", precond="none",
-          debug_breakdown_at=0, stop_margin=0.0):
+          debug_breakdown_at=0, stop_margin=0.0, driver="auto", barrier_spins=0):
     """Solve A x = b on the device.  Returns (x, info dict)."""
     torch = _torch()
     if x is None:
         x = torch.empty(A.n, dtype=torch.float64, device=b.device)
     opts = solve_opts(precision, max_iters, ru_delta, net, chunk, timing, formulation, precond, debug_breakdown_at,
-                      stop_margin)
+                      stop_margin, driver, barrier_spins)
     info = CfdSolveInfo()
     rc = load().cfd_solve(A.handle, _ptr(b, torch.float64, A.n, "b"), _ptr(x0, torch.float64, A.n, "x0"),
                           float(tol), ctypes.byref(opts), _ptr(x, torch.float64, A.n, "x"),
@@ -199,11 +205,11 @@ class State:
 
 
 def step(S: State, dt, tol=1e-10, precision="fp64", net=None, max_iters=0, ru_delta=0.0, chunk=0,
-         formulation="pinned", guess="zero", precond="none", stop_margin=0.0):
+         formulation="pinned", guess="zero", precond="none", stop_margin=0.0, driver="auto"):
     """One time step (cfd_step).  guess: "zero" (or the network's prediction
     when net is given) or "previous" (start from the pressure in S.p)."""
     opts = solve_opts(precision, max_iters, ru_delta, net, chunk, False, formulation, precond,
-                      stop_margin=stop_margin)
+                      stop_margin=stop_margin, driver=driver)
     if guess not in ("zero", "previous"):
         raise ValueError("guess must be 'zero' or 'previous'")
     opts.step_guess = 1 if guess == "previous" else 0

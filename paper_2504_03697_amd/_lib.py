@@ -23,7 +23,8 @@ class CfdSolveOpts(ctypes.Structure):
                 ("net", ctypes.c_void_p), ("chunk", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("formulation", ctypes.c_int32), ("step_guess", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("debug_breakdown_at", ctypes.c_int32),
-                ("stop_margin", ctypes.c_double)]
+                ("stop_margin", ctypes.c_double), ("driver", ctypes.c_int32),
+                ("barrier_spins", ctypes.c_int32)]
 
 
 class CfdSolveInfo(ctypes.Structure):

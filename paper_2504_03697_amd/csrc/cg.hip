@@ -49,6 +49,20 @@ namespace cfd {
 constexpr int kDefer = 4;
 constexpr int kRing = kDefer;
 
+// Persistent driver.  Each grid barrier costs a few microseconds (every
+// workgroup writes back and invalidates its XCD's L2 so that the others see
+// its writes), which only beats two kernel launches per iteration on the
+// smallest grids: measured per iteration at 16^3 13.3 us against 16.6 (FP64)
+// and 22.2 (mixed) with one launch per step, at 24^3 18.1-18.7 against
+// 18.7-21.4, at 32^3 21.9-23.6 against 18.7-20.7.  So grids up to 24^3 cells
+// use it by default (CFD_DRIVER_AUTO).  At most 32 workgroups take part
+// (fewer barrier arrivals; measured best from 24^3 to 64^3).  A barrier wait
+// gives up after kBarrierSpins polls (about 0.3 s; a step of such a grid
+// takes microseconds).
+constexpr int64_t kPersistMaxRows = 24 * 24 * 24;
+constexpr int kPersistMaxGroups = 32;
+constexpr int64_t kBarrierSpins = 1 << 22;
+
 // Default stopping margin of the mixed path (see stop_margin()).
 constexpr double kMixedStopMargin = 0.05;
 
@@ -103,6 +117,8 @@ struct SolveArgs {
     float *p32[kRing];      // mixed: ring of direction buffers
     double *partA, *partB, *partF, *partF2, *partG1, *partG2, *partFp, *partS;
     CgState *S;
+    unsigned *bar;          // persistent driver: grid barrier [arrivals, generation, error]
+    int64_t spin_limit;     // persistent driver: polls before a barrier wait gives up
 };
 
 struct Workspace {
@@ -114,6 +130,7 @@ struct Workspace {
     double *y = nullptr;
     double *c = nullptr;     // consistent right-hand side (projected formulation)
     double *part = nullptr;  // 9 * gmax doubles
+    unsigned *bar = nullptr; // grid barrier of the persistent driver
     CgState *S = nullptr;
     CgState *host = nullptr; // pinned, 2 entries
     hipEvent_t ev0 = nullptr, ev1 = nullptr, evc[2] = {nullptr, nullptr};
@@ -132,6 +149,7 @@ void workspace_free(Workspace *ws) {
     for (float *p : ff) if (p) (void)hipFree(p);
     for (float *p : ws->p32) if (p) (void)hipFree(p);
     if (ws->S) (void)hipFree(ws->S);
+    if (ws->bar) (void)hipFree(ws->bar);
     if (ws->host) (void)hipHostFree(ws->host);
     hipEvent_t ee[] = {ws->ev0, ws->ev1, ws->evc[0], ws->evc[1]};
     for (hipEvent_t e : ee) if (e) (void)hipEventDestroy(e);
@@ -158,6 +176,7 @@ static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm, bool 
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = alloc(&w->part, (int64_t)w->gmax * 9);
     if (e == hipSuccess) e = alloc(&w->S, 2);
+    if (e == hipSuccess) e = alloc(&w->bar, 4);
     if (e == hipSuccess && !w->host) e = hipHostMalloc((void **)&w->host, sizeof(CgState) * 2, 0);
     if (e == hipSuccess) e = alloc(&w->r, n);
     if (fp64) {
@@ -294,6 +313,7 @@ __global__ void __launch_bounds__(kBlock) cg_init(SolveArgs a, int64_t t) {
         ns.fallback = fallback;
         ns.xpin = xg((int32_t)a.pin);
         a.S[(t + 1) & 1] = ns;
+        if (a.bar) a.bar[0] = a.bar[1] = a.bar[2] = 0u;  // fresh grid barrier for the persistent driver
     }
 }
 
@@ -432,31 +452,32 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     return D;
 }
 
-// A kernel, float64.  Normal: x += alpha p_old; p = r + beta p_old; q = A p.
+// Bodies of the solver's kernels, shared by the launch-per-step driver (one
+// kernel per step, below) and the persistent driver (cg_persist): each takes
+// the control state every workgroup holds and returns the next one (the same
+// bits in every thread).
+
+// The solve has ended (float64): x = 0 (b == 0) or x with the pending update
+// folded in, plus the projected formulation's shift.
+__device__ __forceinline__ void a64_final(const SolveArgs &a, const CgState &st, const Decision &D) {
+    const double *pold = st.pcur ? a.p1 : a.p0;
+    const double alpha = st.alpha;
+    if (D.zero_x || D.fold || a.proj)
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
+            a.x[i] = D.zero_x ? 0.0
+                   : (a.proj && i == a.pin) ? a.b[a.pin]
+                   : (D.fold ? folded64(a, i, alpha, pold) : a.x[i]) + D.shift;
+}
+
+// A step, float64.  Normal: x += alpha p_old; p = r + beta p_old; q = A p.
 // Init/refresh: (fold x) p = r; q = A p.  The matrix values come from the
 // float32 copy: they are small integers, so each float64 product, and the
 // result, is bit-identical to the one with the float64 copy, at 4 B per entry
 // less.  The same holds for every kernel of the solver that reads values.
-__global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
-    CG_SHARED(float);
-    const CgState st = a.S[t & 1];
-    CgState *out = &a.S[(t + 1) & 1];
-    if (st.done || st.pending) {
-        if (lead()) *out = st;
-        return;
-    }
-    const Decision D = decide<false>(a, st, red);
+__device__ __forceinline__ CgState a64_body(const SolveArgs &a, const CgState &st, const Decision &D, double *red,
+                                            int32_t *s_col, float *s_val) {
     const double *pold = st.pcur ? a.p1 : a.p0;
     const double alpha = st.alpha;  // pending update (normal mode or refresh fold)
-    if (D.stop) {
-        if (D.ns.done && (D.zero_x || D.fold || a.proj))
-            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
-                a.x[i] = D.zero_x ? 0.0
-                       : (a.proj && i == a.pin) ? a.b[a.pin]
-                       : (D.fold ? folded64(a, i, alpha, pold) : a.x[i]) + D.shift;
-        if (lead()) *out = D.ns;
-        return;
-    }
     double *pnew = st.pcur ? a.p0 : a.p1;
     const bool normal = st.mode == MODE_NORMAL;
     const bool fold = normal || D.fold;
@@ -475,23 +496,15 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     });
     pq = block_sum(pq, red);
     if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
-    if (lead()) {
-        CgState ns = D.ns;
-        ns.mode = MODE_NORMAL;
-        ns.iters = st.iters + 1;
-        ns.pcur = 1 - st.pcur;
-        ns.alpha = 0.0;
-        *out = ns;
-    }
+    CgState ns = D.ns;
+    ns.mode = MODE_NORMAL;
+    ns.iters = st.iters + 1;
+    ns.pcur = 1 - st.pcur;
+    ns.alpha = 0.0;
+    return ns;
 }
 
-// A kernel, mixed.  Normal: p = r + beta p_old; q = A p (float32).
-// Init/refresh: r = r64 / s_new; p = r + cref p_old; q = A p.  x is written
-// only when the solve ends (queued updates, projected shift); the B kernels
-// apply the queue otherwise.
-// The kernel is latency-bound: 8 resident workgroups per CU (the most a
-// SIMD can hold, 64 VGPRs per lane) measured fastest at 256^3.
-__global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
+__global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
     CG_SHARED(float);
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
@@ -499,18 +512,34 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
         if (lead()) *out = st;
         return;
     }
-    const Decision D = decide<true>(a, st, red);
-    const float *pold = ring(a, st.pcur);
+    const Decision D = decide<false>(a, st, red);
     if (D.stop) {
-        if (D.ns.done && (D.zero_x || st.npend > 0 || a.proj))
-            for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
-                a.x[i] = D.zero_x ? 0.0
-                       : (a.proj && i == a.pin) ? a.b[a.pin]
-                       : folded32(a, st, i) + D.shift;
-            }
+        if (D.ns.done) a64_final(a, st, D);
         if (lead()) *out = D.ns;
         return;
     }
+    const CgState ns = a64_body(a, st, D, red, s_col, s_val);
+    if (lead()) *out = ns;
+}
+
+// The solve has ended (mixed): x = 0, or x plus the queued updates, plus the
+// projected formulation's shift.
+__device__ __forceinline__ void a32_final(const SolveArgs &a, const CgState &st, const Decision &D) {
+    if (D.zero_x || st.npend > 0 || a.proj)
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+            a.x[i] = D.zero_x ? 0.0
+                   : (a.proj && i == a.pin) ? a.b[a.pin]
+                   : folded32(a, st, i) + D.shift;
+        }
+}
+
+// A step, mixed.  Normal: p = r + beta p_old; q = A p (float32).
+// Init/refresh: r = r64 / s_new; p = r + cref p_old; q = A p.  x is written
+// only when the solve ends (queued updates, projected shift); the B steps
+// apply the queue otherwise.
+__device__ __forceinline__ CgState a32_body(const SolveArgs &a, const CgState &st, const Decision &D, double *red,
+                                            int32_t *s_col, float *s_val) {
+    const float *pold = ring(a, st.pcur);
     float *pnew = const_cast<float *>(ring(a, (st.pcur + 1) % kRing));
     const bool normal = st.mode == MODE_NORMAL;
     const bool use_p = normal || st.mode == MODE_REFRESH;
@@ -532,41 +561,49 @@ __global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
     });
     pq = block_sum(pq, red);
     if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
-    if (lead()) {
-        CgState ns = D.ns;
-        ns.mode = MODE_NORMAL;
-        ns.iters = st.iters + 1;
-        ns.pcur = (st.pcur + 1) % kRing;
-        ns.alpha = 0.0;
-        *out = ns;
-    }
+    CgState ns = D.ns;
+    ns.mode = MODE_NORMAL;
+    ns.iters = st.iters + 1;
+    ns.pcur = (st.pcur + 1) % kRing;
+    ns.alpha = 0.0;
+    return ns;
 }
 
-// B kernel: alpha = rho / p^T q; r -= alpha q; partial sums of r^T r.
-template <bool MIXED>
-__global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
-    __shared__ double red[kBlock / 64];
+// A kernel, mixed.  The kernel is latency-bound: 8 resident workgroups per CU
+// (the most a SIMD can hold, 64 VGPRs per lane) measured fastest at 256^3.
+__global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
+    CG_SHARED(float);
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
     if (st.done || st.pending) {
         if (lead()) *out = st;
         return;
     }
+    const Decision D = decide<true>(a, st, red);
+    if (D.stop) {
+        if (D.ns.done) a32_final(a, st, D);
+        if (lead()) *out = D.ns;
+        return;
+    }
+    const CgState ns = a32_body(a, st, D, red, s_col, s_val);
+    if (lead()) *out = ns;
+}
+
+// B step: alpha = rho / p^T q; r -= alpha q; partial sums of r^T r.
+template <bool MIXED>
+__device__ __forceinline__ CgState b_body(const SolveArgs &a, const CgState &st, double *red) {
     const double pq = reduce_partials(a.partA, a.Ga, red);
     const double alpha = st.rho / pq;
     if (!(pq > 0.0) || !std::isfinite(alpha) || st.iters == a.break_at) {
-        if (lead()) {
-            CgState ns = st;
-            ns.pending = 1;
-            ns.reason = R_BREAKDOWN;
-            ns.alpha = 0.0;
-            // mixed: this iteration's direction is not queued, so the newest
-            // queued update is the one before it; point pcur back at it
-            // (pend_slot() counts the queue back from pcur)
-            if (MIXED) ns.pcur = (st.pcur - 1 + kRing) % kRing;
-            *out = ns;
-        }
-        return;
+        CgState ns = st;
+        ns.pending = 1;
+        ns.reason = R_BREAKDOWN;
+        ns.alpha = 0.0;
+        // mixed: this iteration's direction is not queued, so the newest
+        // queued update is the one before it; point pcur back at it
+        // (pend_slot() counts the queue back from pcur)
+        if (MIXED) ns.pcur = (st.pcur - 1 + kRing) % kRing;
+        return ns;
     }
     double rr = 0.0;
     double sa_new = 0.0;
@@ -653,21 +690,32 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
     }
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) a.partB[blockIdx.x] = rr;
-    if (lead()) {
-        CgState ns = st;
-        ns.alpha = alpha;
-        if (MIXED) {
-            if (st.npend < kDefer - 1) {
+    CgState ns = st;
+    ns.alpha = alpha;
+    if (MIXED) {
+        if (st.npend < kDefer - 1) {
 #pragma unroll
-                for (int e = 0; e < kDefer - 1; ++e)
-                    if (e == st.npend) ns.sa[e] = sa_new;
-                ns.npend = st.npend + 1;
-            } else {
-                ns.npend = 0;  // applied above
-            }
+            for (int e = 0; e < kDefer - 1; ++e)
+                if (e == st.npend) ns.sa[e] = sa_new;
+            ns.npend = st.npend + 1;
+        } else {
+            ns.npend = 0;  // applied above
         }
-        *out = ns;
     }
+    return ns;
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
+    __shared__ double red[kBlock / 64];
+    const CgState st = a.S[t & 1];
+    CgState *out = &a.S[(t + 1) & 1];
+    if (st.done || st.pending) {
+        if (lead()) *out = st;
+        return;
+    }
+    const CgState ns = b_body<MIXED>(a, st, red);
+    if (lead()) *out = ns;
 }
 
 // F kernel: when a refresh is pending, r = c - A x' in float64 with the
@@ -675,14 +723,8 @@ __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
 // s alpha p (mixed) gathered on the fly.  x itself is only written by the next A kernel (which
 // never gathers x), so no workgroup can see a half-updated x here.
 template <bool MIXED>
-__global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
-    CG_SHARED(float);
-    const CgState st = a.S[t & 1];
-    CgState *out = &a.S[(t + 1) & 1];
-    if (st.done || !st.pending) {
-        if (lead()) *out = st;
-        return;
-    }
+__device__ __forceinline__ CgState f_body(const SolveArgs &a, const CgState &st, double *red, int32_t *s_col,
+                                          float *s_val) {
     const double alpha = st.alpha;
     const double *p64 = st.pcur ? a.p1 : a.p0;
     auto xg = [&](int32_t j) -> double {
@@ -703,14 +745,110 @@ __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
         a.partF[blockIdx.x] = rr;
         a.partFp[blockIdx.x] = rp;
     }
-    if (lead()) {
-        CgState ns = st;
-        ns.pending = 0;
-        ns.mode = MODE_REFRESH;
-        ns.updates = st.updates + 1;
-        ns.xpin = xg((int32_t)a.pin);  // nobody writes x, p or d in this kernel
-        *out = ns;
+    CgState ns = st;
+    ns.pending = 0;
+    ns.mode = MODE_REFRESH;
+    ns.updates = st.updates + 1;
+    ns.xpin = xg((int32_t)a.pin);  // nobody writes x, p or d in this step
+    return ns;
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
+    CG_SHARED(float);
+    const CgState st = a.S[t & 1];
+    CgState *out = &a.S[(t + 1) & 1];
+    if (st.done || !st.pending) {
+        if (lead()) *out = st;
+        return;
     }
+    const CgState ns = f_body<MIXED>(a, st, red, s_col, s_val);
+    if (lead()) *out = ns;
+}
+
+// ---------------------------------------------------------------- persistent driver
+//
+// One cooperative launch runs the whole iteration: every workgroup is
+// resident, and the steps that the launch-per-step driver puts in separate
+// kernels (A, B, refresh) are separated by grid barriers instead.  Every
+// workgroup keeps the control state itself: the decisions are taken from
+// partial sums reduced in a fixed order, so all workgroups hold the same bits
+// and leave the loop together.  For grids small enough that the launches,
+// not the memory traffic, set the iteration time.
+
+// Grid barrier: arrivals are counted in bar[0]; the last to arrive resets the
+// count and advances the generation in bar[1], which the others poll.  The
+// fences before arriving and after leaving make every write issued before the
+// barrier visible to every workgroup after it (agent scope: across the XCDs'
+// L2 caches).  The wait is bounded: after spin_limit polls it sets bar[2]
+// and fails, and so does every barrier after it, so all workgroups leave.
+__device__ inline bool grid_sync(const SolveArgs &a, unsigned &seen) {
+    __shared__ int ok_s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned *count = a.bar, *gen = a.bar + 1, *err = a.bar + 2;
+        const unsigned target = seen + 1;
+        __threadfence();
+        if (atomicAdd(count, 1u) == gridDim.x - 1) {
+            atomicExch(count, 0u);
+            __threadfence();
+            atomicExch(gen, target);
+        } else {
+            int64_t spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > a.spin_limit) {
+                    atomicExch(err, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
+        seen = target;
+        ok_s = ok;
+    }
+    __syncthreads();
+    return ok_s != 0;
+}
+
+// The same steps, decisions and arithmetic as the launch-per-step driver
+// (with one grid size for every step, so the partial sums group differently).
+// Reads the state cg_init left in S[t & 1], writes the final one to
+// S[(t + 1) & 1]; x is written before it returns.
+template <bool MIXED>
+__global__ void __launch_bounds__(kBlock) cg_persist(SolveArgs a, int64_t t) {
+    CG_SHARED(float);
+    CgState st = a.S[t & 1];
+    unsigned seen = 0;
+    bool ok = true;
+    while (!st.done) {
+        if (st.pending) {
+            st = f_body<MIXED>(a, st, red, s_col, s_val);
+            if (!(ok = grid_sync(a, seen))) break;
+            continue;
+        }
+        const Decision D = decide<MIXED>(a, st, red);
+        if (D.stop) {
+            if (D.ns.done) {
+                if (MIXED) a32_final(a, st, D);
+                else a64_final(a, st, D);
+            }
+            st = D.ns;
+            continue;
+        }
+        st = MIXED ? a32_body(a, st, D, red, s_col, s_val) : a64_body(a, st, D, red, s_col, s_val);
+        if (!(ok = grid_sync(a, seen))) break;
+        st = b_body<MIXED>(a, st, red);
+        if (!(ok = grid_sync(a, seen))) break;
+    }
+    if (!ok) {
+        st.done = 1;
+        st.status = CFD_EHIP;
+    }
+    if (lead()) a.S[(t + 1) & 1] = st;
 }
 
 // Warm start: partial sums of y^T A y and c^T y for gamma, with y[pin] = 0
@@ -799,6 +937,39 @@ static double stop_margin(const cfd_solve_opts &opts) {
     return opts.precision == CFD_PREC_MIXED ? kMixedStopMargin : 1.0;
 }
 
+// Run the persistent driver after cg_init (launch sequence number t) and
+// fill info.  The whole solve is one launch, so no per-launch timings.
+static int persist_run(SolveArgs &a, bool mixed, int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s) {
+    void *args[] = {(void *)&a, (void *)&t};
+    const void *kern = mixed ? (const void *)cg_persist<true> : (const void *)cg_persist<false>;
+    CFD_HIP(hipLaunchCooperativeKernel(kern, dim3(a.Ga), dim3(kBlock), args, 0, s));
+    CFD_HIP(hipMemcpyAsync(&w->host[0], &w->S[(t + 1) & 1], sizeof(CgState), hipMemcpyDeviceToHost, s));
+    CFD_HIP(hipEventRecord(w->ev1, s));
+    CFD_HIP(hipEventSynchronize(w->ev1));
+    float ms = 0.0f;
+    CFD_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    const CgState fs = w->host[0];
+    cfd_solve_info inf{};
+    inf.iters = fs.iters;
+    inf.updates = fs.updates;
+    inf.status = fs.done ? fs.status : CFD_EHIP;
+    inf.used_fallback = fs.fallback;
+    inf.rel_residual = fs.relres;
+    inf.init_residual = fs.init_relres;
+    inf.gamma = fs.gamma;
+    inf.seconds = ms * 1e-3;
+    if (info) *info = inf;
+    if (inf.status != CFD_OK) {
+        const char *what = inf.status == CFD_ENOCONV ? "max_iters reached"
+                         : inf.status == CFD_EBREAKDOWN ? "breakdown: p^T A p <= 0"
+                         : inf.status == CFD_ENONFINITE ? "non-finite value in the solve"
+                         : inf.status == CFD_EHIP ? "persistent driver: a grid barrier wait timed out"
+                                                  : "solver error";
+        return fail(inf.status, std::string("cfd_solve: ") + what);
+    }
+    return CFD_OK;
+}
+
 static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts *o,
                       double *x, cfd_solve_info *info, hipStream_t s) {
     cfd_solve_opts opts{};
@@ -873,6 +1044,29 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.partFp = w->part + 7 * gm;
     a.partS = w->part + 8 * gm;
     a.S = w->S;
+    a.bar = w->bar;
+    a.spin_limit = opts.barrier_spins > 0 ? opts.barrier_spins : kBarrierSpins;
+
+    // Driver: one cooperative launch for the whole iteration (small grids,
+    // where launches set the pace), or one launch per step.
+    if (opts.driver != CFD_DRIVER_AUTO && opts.driver != CFD_DRIVER_STEPS && opts.driver != CFD_DRIVER_PERSISTENT)
+        return fail(CFD_EINVAL, "cfd_solve: unknown driver");
+    bool persist = opts.driver == CFD_DRIVER_PERSISTENT || (opts.driver == CFD_DRIVER_AUTO && A->n <= kPersistMaxRows);
+    if (persist) {
+        int coop = 0;
+        CFD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, A->device));
+        if (!coop) {
+            if (opts.driver == CFD_DRIVER_PERSISTENT)
+                return fail(CFD_EINVAL, "cfd_solve: the device does not support cooperative launches");
+            persist = false;
+        }
+    }
+    if (persist) {
+        // every step on one grid that is resident all at once
+        const int G = std::min(kPersistMaxGroups,
+                               grid_tiles(A->n, mixed ? resident_per_cu(cg_persist<true>) : resident_per_cu(cg_persist<false>)));
+        a.Ga = a.Gb = a.Gf = G;
+    }
 
     CFD_HIP(hipEventRecord(w->ev0, s));
     if (opts.net) {
@@ -888,6 +1082,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     else hipLaunchKernelGGL(cg_init<false>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
     ++t;
     CFD_HIP(hipGetLastError());
+    if (persist) return persist_run(a, mixed, t, w, info, s);
 
     // Enqueue chunks of K iterations + one refresh kernel; poll the state of
     // the previous chunk while the current one runs.

@@ -23,7 +23,7 @@ def test_every_declared_symbol_is_exported():
 def test_struct_layouts_match_header_sizes():
     # cfd_grid: 3 int32 + pad + double; solve opts/info are 8-byte aligned
     assert ctypes.sizeof(_lib.CfdGrid) == 24
-    assert ctypes.sizeof(_lib.CfdSolveOpts) == 56
+    assert ctypes.sizeof(_lib.CfdSolveOpts) == 64
     assert ctypes.sizeof(_lib.CfdSolveInfo) == 64
 
 

@@ -608,3 +608,97 @@ def test_solve_timing_samples(lib):
     x, info = lib.solve(A, b, timing=True)
     assert info["spmv_samples"] >= 1 and info["spmv_ms"] > 0
     assert info["seconds"] > 0
+
+
+# ---------------------------------------------------------------- persistent driver
+
+@pytest.mark.parametrize("dims,kind,seed", CASES + [((40, 40, 40), "uniform", 9), ((1, 1, 1), "uniform", 0),
+                                             ((2, 3, 1), "uniform", 1), ((64, 64, 64), "smoothed", 4)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("formulation", ["pinned", "projected"])
+def test_persistent_driver_parity(lib, dims, kind, seed, precision, formulation):
+    """The persistent driver (one cooperative launch, grid barriers between
+    the steps) against the oracle: the same bars as the launch-per-step
+    driver, and the same iteration count up to the rounding of different
+    partial-sum groupings (float64: 2 % + 2; mixed: 10 % + 5)."""
+    tol = 1e-10
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, kind, seed)
+    truth = oracle.cg(ref, b, tol=1e-13)[0]
+    A = lib.assemble(dims, 0)
+    print(f"persistent {dims} {kind} {seed} {precision} {formulation}", flush=True)
+    x, info = lib.solve(A, dev(b), tol=tol, precision=precision, formulation=formulation, driver="persistent")
+    x = host(x)
+    assert info["status"] == 0
+    if not np.any(b):
+        assert not np.any(x) and info["iters"] == 0
+        return
+    stop = tol * (0.05 if precision == "mixed" else 1.0)
+    assert info["rel_residual"] <= stop
+    rr = true_relres(ref, b, x)
+    assert rr <= stop + relres_rounding(ref, b, x)
+    assert abs(rr - info["rel_residual"]) <= 0.05 * stop + relres_rounding(ref, b, x)
+    if ref.n > 1:
+        assert mean_removed_err(x, truth) <= 1e-9
+    _, it_steps = lib.solve(A, dev(b), tol=tol, precision=precision, formulation=formulation, driver="steps")
+    # float64: the same iteration up to rounding; mixed: float32 rounding of
+    # different partial-sum groupings moves the count further
+    slack = 2 + 0.02 * it_steps["iters"] if precision == "fp64" else 5 + 0.1 * it_steps["iters"]
+    assert abs(info["iters"] - it_steps["iters"]) <= slack, (info["iters"], it_steps["iters"])
+    if precision == "fp64" and formulation == "pinned":
+        _, it_ora, _, st = oracle.cg(ref, b, tol=tol)
+        assert abs(info["iters"] - it_ora) <= 2 + 0.02 * it_ora, (info["iters"], it_ora)
+
+
+def test_persistent_driver_warm_start_and_errors(lib):
+    """Persistent driver with a warm-start network and with x0, b = 0, the
+    iteration cap and a breakdown: the same outcomes as the launch-per-step
+    driver."""
+    from paper_2504_03697_amd._lib import CFD_EBREAKDOWN, CFD_ENOCONV
+    dims = (20, 18, 22)
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, "uniform", 8)
+    A = lib.assemble(dims, 0)
+    bd = dev(b)
+    net = lib.Net(synth.net_init(3))
+    for drv in ("steps", "persistent"):
+        x, info = lib.solve(A, bd, tol=1e-10, precision="mixed", formulation="projected", net=net, driver=drv)
+        assert info["status"] == 0 and info["gamma"] != 0.0
+        assert true_relres(ref, b, host(x)) <= 0.05e-10 + relres_rounding(ref, b, host(x))
+    x0 = dev(synth.uniform_rhs(dims, 9))
+    xs, i_s = lib.solve(A, bd, x0=x0, tol=1e-10, precision="fp64", driver="steps")
+    xp, i_p = lib.solve(A, bd, x0=x0, tol=1e-10, precision="fp64", driver="persistent")
+    assert abs(i_s["iters"] - i_p["iters"]) <= 2
+    np.testing.assert_allclose(host(xp), host(xs), rtol=0, atol=1e-8 * np.abs(host(xs)).max())
+    # deterministic: every decision comes from fixed-order sums
+    x1, i1 = lib.solve(A, bd, tol=1e-10, precision="mixed", driver="persistent")
+    x2, i2 = lib.solve(A, bd, tol=1e-10, precision="mixed", driver="persistent")
+    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
+    z, iz = lib.solve(A, dev(np.zeros(ref.n)), tol=1e-10, precision="mixed", driver="persistent")
+    assert iz["iters"] == 0 and not np.any(host(z))
+    xc, ic = lib.solve(A, bd, tol=1e-10, precision="mixed", max_iters=30, driver="persistent", raise_on_error=False)
+    assert ic["rc"] == CFD_ENOCONV and ic["iters"] == 30
+    x64p, _ = lib.solve(A, bd, tol=1e-10, precision="fp64", max_iters=30, driver="persistent", raise_on_error=False)
+    x64s, _ = lib.solve(A, bd, tol=1e-10, precision="fp64", max_iters=30, driver="steps", raise_on_error=False)
+    assert np.abs(host(x64p) - host(x64s)).max() <= 1e-10 * np.abs(host(x64s)).max()
+    xb, ib = lib.solve(A, bd, tol=1e-10, precision="mixed", debug_breakdown_at=31, driver="persistent",
+                       raise_on_error=False)
+    assert ib["rc"] == CFD_EBREAKDOWN and ib["iters"] == 31
+    assert np.array_equal(host(xb), host(xc))
+
+
+def test_persistent_driver_barrier_timeout_is_an_error(lib):
+    """A grid barrier that waits longer than its poll limit ends the solve
+    with CFD_EHIP instead of waiting on (forced here with a one-poll limit:
+    every workgroup still leaves the kernel), and the next solve on the same
+    handle is unaffected."""
+    from paper_2504_03697_amd._lib import CFD_EHIP
+    dims = (16, 16, 16)  # 16 workgroups
+    b = make_rhs(dims, "uniform", 0)
+    A = lib.assemble(dims, 0)
+    bd = dev(b)
+    x, info = lib.solve(A, bd, tol=1e-10, precision="fp64", driver="persistent", barrier_spins=1,
+                        raise_on_error=False)
+    assert info["rc"] == CFD_EHIP
+    x, info = lib.solve(A, bd, tol=1e-10, precision="fp64", driver="persistent")
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
