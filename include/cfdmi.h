@@ -199,14 +199,19 @@ typedef struct cfd_solve_opts {
                             CFD_EBREAKDOWN and the iterate of k-1 updates
                             (the error path, exercised on demand).        */
     double  stop_margin; /* the solve runs until the float64 true residual
-                            is <= stop_margin * tol * ||b||; <= 0 means the
-                            default: 0.05 for CFD_PREC_MIXED, 1 for
-                            CFD_PREC_FP64 (values > 1 act as 1).  float32
-                            rounding noise leaves error in the lowest modes
-                            that a residual at tol does not show: on white-
-                            noise and cavity right-hand sides the mixed path
-                            measured 1e-9..3e-8 relative pressure error at a
-                            1e-10 residual, <= 3e-10 at 0.05 * 1e-10.      */
+                            is <= stop_margin * tol * ||b|| (values > 1 act
+                            as 1).  <= 0 means the default: CFD_PREC_FP64 1;
+                            CFD_PREC_MIXED 0.05 when the right-hand side's
+                            Rayleigh quotient b^T A b / b^T b exceeds 0.5,
+                            else 1 (computed on the device, one sweep).
+                            float32 rounding noise leaves error in the
+                            lowest modes that a residual at tol does not
+                            show, most where b holds little of them: at a
+                            1e-10 residual the mixed path measured <= 1.3e-10
+                            relative pressure error on smooth right-hand
+                            sides (quotient ~0.16), 0.4e-9..1.4e-9 on cavity
+                            steps (~2) and 1e-9..3e-8 on white noise (~6);
+                            <= 3e-10 on all of them at 0.05 * 1e-10.       */
     int32_t driver;      /* unpreconditioned solves only (the DIC path always
                             launches per step):
                             CFD_DRIVER_STEPS: one kernel launch per step
@@ -236,6 +241,8 @@ typedef struct cfd_solve_info {
     double  spmv_ms;        /* mean duration of the sampled CG SpMV launches  */
     int32_t spmv_samples;   /* number of launches behind spmv_ms              */
     int32_t pad_;
+    double  stop_margin;    /* the stopping margin this solve applied (the
+                               true residual was taken to <= stop_margin*tol) */
 } cfd_solve_info;
 
 /*
@@ -307,6 +314,19 @@ void cfd_net_destroy(cfd_net_t net);
 
 /* y = s * f(b/s), s = rms(b) (y = 0 when b = 0).  b, y: device double[n]. */
 int cfd_net_forward(cfd_net_t net, const cfd_grid *grid, const double *b, double *y, void *stream);
+
+/*
+ * One training pair of the warm start from a right-hand side b and its
+ * pressure p (device double[n]): input = b / rms(b) and target =
+ * (p - mean p) / rms(p - mean p), device float[n] each (0 where the divisor
+ * is 0).  The network is bias-free, hence positively homogeneous, so the
+ * input scale loses nothing; the target scale does not matter to the solver
+ * either (the prediction is rescaled by the A-optimal factor), and unit RMS
+ * keeps the loss of every pair and every grid size at the same scale.  Uses
+ * the network's scratch; does not synchronise.
+ */
+int cfd_net_training_pair(cfd_net_t net, const cfd_grid *grid, const double *b, const double *p,
+                          float *input, float *target, void *stream);
 
 /*
  * One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the

@@ -21,7 +21,7 @@ Functions and the passage each follows:
 * ``step``          - Sec. 3.1 fractional step (forces, semi-Lagrangian
                       advection, pressure correction) on the staggered grid,
                       plus explicit viscosity (Sec. 5 future-work item).
-* ``conv3d_*``, ``net_*``, ``adam``, ``round_bf16`` - the learned warm
+* ``conv3d_*``, ``net_*``, ``adam``, ``round_bf16``, ``training_pair`` - the learned warm
                       start's network (not in the paper; definitions written
                       out directly; its activations are stored in bfloat16).
 """
@@ -408,6 +408,20 @@ def net_loss_grad(grid, x, target, theta, shapes):
         if l > 0:
             g = conv3d_bwd_data(grid, g, Ws[l], cin, cout)
     return loss, np.concatenate(grads)
+
+
+def training_pair(b, p):
+    """Warm-start training pair (written out from its definition, float64,
+    returned as float32): input b / rms(b), target (p - mean p) /
+    rms(p - mean p); zero where the divisor is zero."""
+    b = _f64(b)
+    p = _f64(p)
+    rb = np.sqrt(np.mean(b * b))
+    d = p - np.mean(p)
+    rp = np.sqrt(np.mean(d * d))
+    x = b / rb if rb > 0 else np.zeros_like(b)
+    t = d / rp if rp > 0 else np.zeros_like(d)
+    return x.astype(np.float32), t.astype(np.float32)
 
 
 def adam(theta, m, v, g, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -251,6 +251,20 @@ class Net:
                                      _ptr(y, torch.float64, n, "y"), _stream()))
         return y
 
+    def training_pair(self, dims, b, p, inp=None, target=None):
+        """cfd_net_training_pair: (b / rms b, (p - mean p) / rms(p - mean p)) as float32."""
+        torch = _torch()
+        g = make_grid(dims)
+        n = g.nx * g.ny * g.nz
+        if inp is None:
+            inp = torch.empty(n, dtype=torch.float32, device=b.device)
+        if target is None:
+            target = torch.empty(n, dtype=torch.float32, device=b.device)
+        check(load().cfd_net_training_pair(self._h, ctypes.byref(g), _ptr(b, torch.float64, n, "b"),
+                                           _ptr(p, torch.float64, n, "p"), _ptr(inp, torch.float32, n, "input"),
+                                           _ptr(target, torch.float32, n, "target"), _stream()))
+        return inp, target
+
     def train_step(self, dims, inp, target, lr, batch=None):
         torch = _torch()
         g = make_grid(dims)

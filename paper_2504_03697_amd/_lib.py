@@ -31,7 +31,8 @@ class CfdSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("updates", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("used_fallback", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("init_residual", ctypes.c_double), ("gamma", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("spmv_ms", ctypes.c_double), ("spmv_samples", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("spmv_ms", ctypes.c_double), ("spmv_samples", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("stop_margin", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
@@ -83,6 +84,7 @@ def load():
         "cfd_net_forward": (i32, [vp, P(CfdGrid), vp, vp, vp]),
         "cfd_net_train_step": (i32, [vp, P(CfdGrid), i32, vp, vp, flt, P(flt), vp]),
         "cfd_net_gradient": (i32, [vp, P(CfdGrid), i32, vp, vp, vp, P(flt), vp]),
+        "cfd_net_training_pair": (i32, [vp, P(CfdGrid), vp, vp, vp, vp, vp]),
         "cfd_net_get_params": (i32, [vp, vp, i64]),
         "cfd_net_set_params": (i32, [vp, vp, i64]),
         "cfd_conv3d_forward": (i32, [P(CfdGrid), i32, i32, vp, vp, vp, i32, vp]),

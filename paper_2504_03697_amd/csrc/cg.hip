@@ -63,8 +63,20 @@ constexpr int64_t kPersistMaxRows = 24 * 24 * 24;
 constexpr int kPersistMaxGroups = 32;
 constexpr int64_t kBarrierSpins = 1 << 22;
 
-// Default stopping margin of the mixed path (see stop_margin()).
+// Stopping margin: the solve runs until the true residual reaches
+// tol * margin.  float32 rounding leaves error in the lowest modes that a
+// residual at tol cannot show (their share of the residual is lambda_min
+// times their share of the error), and it weighs most where b, hence x,
+// holds little of those modes: measured at a 1e-10 residual, the mixed
+// path's pressure error was <= 1.3e-10 on Gaussian-smoothed right-hand sides
+// (128^3, 256^3), but 0.4e-9..1.4e-9 on cavity steps and 1e-9..3e-8 on white
+// noise (96^3-160^3); with margin 0.05 all were <= 3e-10.  The Rayleigh
+// quotient b^T A b / b^T b tells them apart: 0.16 smoothed, ~2 cavity, ~6
+// white noise.  So the mixed path's default margin is 0.05 when it exceeds
+// kRoughRq, else 1; float64 CG (the plain method, the oracle's iteration)
+// keeps 1.
 constexpr double kMixedStopMargin = 0.05;
+constexpr double kRoughRq = 0.5;
 
 enum Mode : int32_t { MODE_INIT = 0, MODE_NORMAL = 1, MODE_REFRESH = 2 };
 enum Reason : int32_t { R_NONE = 0, R_CONVERGED = 1, R_REFRESH = 2, R_NOCONV = 3, R_BREAKDOWN = 4, R_NONFINITE = 5 };
@@ -90,6 +102,7 @@ struct CgState {
     double init_relres;
     double gamma;      // warm-start scale
     double xpin;       // folded iterate at the pinned cell (projected formulation)
+    double margin;     // stopping margin of this solve
     double sa[kDefer]; // mixed: step lengths s alpha of the pending updates, oldest first
 };
 
@@ -116,6 +129,8 @@ struct SolveArgs {
     float *r32, *q32;
     float *p32[kRing];      // mixed: ring of direction buffers
     double *partA, *partB, *partF, *partF2, *partG1, *partG2, *partFp, *partS;
+    double *partR, *partRb; // b^T A b and b^T b partial sums (stopping margin)
+    double *tolv;           // [effective tolerance tol * margin, margin], set on the device per solve
     CgState *S;
     unsigned *bar;          // persistent driver: grid barrier [arrivals, generation, error]
     int64_t spin_limit;     // persistent driver: polls before a barrier wait gives up
@@ -129,7 +144,8 @@ struct Workspace {
     float *p32[kRing] = {};
     double *y = nullptr;
     double *c = nullptr;     // consistent right-hand side (projected formulation)
-    double *part = nullptr;  // 9 * gmax doubles
+    double *part = nullptr;  // 11 * gmax doubles
+    double *tolv = nullptr;  // effective tolerance and stopping margin
     unsigned *bar = nullptr; // grid barrier of the persistent driver
     CgState *S = nullptr;
     CgState *host = nullptr; // pinned, 2 entries
@@ -150,6 +166,7 @@ void workspace_free(Workspace *ws) {
     for (float *p : ws->p32) if (p) (void)hipFree(p);
     if (ws->S) (void)hipFree(ws->S);
     if (ws->bar) (void)hipFree(ws->bar);
+    if (ws->tolv) (void)hipFree(ws->tolv);
     if (ws->host) (void)hipHostFree(ws->host);
     hipEvent_t ee[] = {ws->ev0, ws->ev1, ws->evc[0], ws->evc[1]};
     for (hipEvent_t e : ee) if (e) (void)hipEventDestroy(e);
@@ -174,7 +191,8 @@ static int ensure_workspace(cfd_csr_t A, bool fp64, bool mixed, bool warm, bool 
     Workspace *w = A->ws;
     const int64_t n = A->n;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = alloc(&w->part, (int64_t)w->gmax * 9);
+    if (e == hipSuccess) e = alloc(&w->part, (int64_t)w->gmax * 11);
+    if (e == hipSuccess) e = alloc(&w->tolv, 2);
     if (e == hipSuccess) e = alloc(&w->S, 2);
     if (e == hipSuccess) e = alloc(&w->bar, 4);
     if (e == hipSuccess && !w->host) e = hipHostMalloc((void **)&w->host, sizeof(CgState) * 2, 0);
@@ -373,7 +391,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     if (st.mode == MODE_NORMAL) {
         const double rr = reduce_partials(a.partB, a.Gb, red);
         const double nr = sqrt(rr);
-        const double thr = a.tol * st.bnorm;
+        const double thr = a.tolv[0] * st.bnorm;
         int reason = R_NONE;
         if (!std::isfinite(rr)) reason = R_NONFINITE;
         else if (nr * st.scale <= thr) reason = R_CONVERGED;
@@ -397,6 +415,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
         if (st.mode == MODE_INIT) {
             const double bb = reduce_partials(a.partF2, a.Gf, red);
             ns.bnorm = sqrt(bb);
+            ns.margin = a.tolv[1];
         } else {
             D.fold = true;  // refresh (float64 path): this A kernel folds x += alpha p
         }
@@ -416,7 +435,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
         } else {
             ns.relres = trp / bn;
             if (st.mode == MODE_INIT) ns.init_relres = ns.relres;
-            if (trp <= a.tol * bn) {
+            if (trp <= a.tolv[0] * bn) {
                 ns.done = 1;
                 ns.status = CFD_OK;
             } else if (st.reason == R_NOCONV || st.iters >= a.max_iters) {
@@ -875,6 +894,54 @@ __global__ void __launch_bounds__(kBlock) warm_gamma(SolveArgs a) {
     }
 }
 
+// Stopping margin (see kRoughRq): partial sums of b^T A b (the pinned
+// matrix) and b^T b.
+__global__ void __launch_bounds__(kBlock) rhs_rayleigh(SolveArgs a) {
+    __shared__ __align__(16) int32_t s_col[kSlabLds];
+    __shared__ __align__(16) float s_val[kSlabLds];
+    __shared__ double red[kBlock / 64];
+    auto bg = [&](int32_t j) -> double { return a.b[j]; };
+    double bab = 0.0, bb = 0.0;
+    csr_sweep<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, [&](int64_t i, int rs, int re) {
+        const double bi = a.b[i];
+        bab = fma(bi, row_product<double>(s_col, s_val, rs, re, bg), bab);
+        bb = fma(bi, bi, bb);
+    });
+    bab = block_sum(bab, red);
+    bb = block_sum(bb, red);
+    if (threadIdx.x == 0) {
+        a.partR[blockIdx.x] = bab;
+        a.partRb[blockIdx.x] = bb;
+    }
+}
+
+// One workgroup: tolv = [tol * margin, margin]; margin = the caller's when
+// given (> 0), else 0.05 for the mixed path when b^T A b / b^T b > kRoughRq
+// (count > 0: the partial sums of rhs_rayleigh), else 1.
+__global__ void __launch_bounds__(kBlock) stop_tol(SolveArgs a, double fixed, int mixed, int count) {
+    __shared__ double red[kBlock / 64];
+    double m = 1.0;
+    if (fixed > 0.0) {
+        m = fixed < 1.0 ? fixed : 1.0;
+    } else if (mixed) {
+        const double bab = reduce_partials(a.partR, count, red);
+        const double bb = reduce_partials(a.partRb, count, red);
+        m = (bb > 0.0 && bab > kRoughRq * bb) ? kMixedStopMargin : 1.0;
+    }
+    if (threadIdx.x == 0) {
+        a.tolv[0] = a.tol * m;
+        a.tolv[1] = m;
+    }
+}
+
+// Launch the two kernels above for a solve whose natural-order arguments are
+// in g (rp, col, v32, b, n, partR, partRb, tolv, tol, Gf).
+static void launch_stop_tol(const SolveArgs &g, const cfd_solve_opts &opts, bool mixed, hipStream_t s) {
+    const bool rq = opts.stop_margin <= 0.0 && mixed;
+    if (rq) hipLaunchKernelGGL(rhs_rayleigh, dim3(g.Gf), dim3(kBlock), 0, s, g);
+    hipLaunchKernelGGL(stop_tol, dim3(1), dim3(kBlock), 0, s, g, opts.stop_margin, mixed ? 1 : 0, rq ? g.Gf : 0);
+}
+
 // Partial sums of b (projected formulation: sum of b for c_pin).
 __global__ void __launch_bounds__(kBlock) rhs_sum(SolveArgs a) {
     __shared__ double red[kBlock / 64];
@@ -925,17 +992,7 @@ static const Grids &solver_grids() {
 static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol, const cfd_solve_opts &opts,
                          double *x, cfd_solve_info *info, hipStream_t s);
 
-// The solve stops when the true residual reaches tol * margin.  float32
-// rounding leaves error in the lowest modes that a residual at tol cannot
-// show (their share of the residual is lambda_min times their share of the
-// error): on white-noise and cavity right-hand sides the mixed path measured
-// 1e-9..3e-8 pressure error at a 1e-10 residual, and <= 3e-10 once it goes
-// on to 0.05 tol (96^3..160^3, both formulations).  float64 CG keeps margin
-// 1: it is the plain method, the same iteration as the oracle's.
-static double stop_margin(const cfd_solve_opts &opts) {
-    if (opts.stop_margin > 0.0) return std::min(opts.stop_margin, 1.0);
-    return opts.precision == CFD_PREC_MIXED ? kMixedStopMargin : 1.0;
-}
+
 
 // Run the persistent driver after cg_init (launch sequence number t) and
 // fill info.  The whole solve is one launch, so no per-launch timings.
@@ -957,6 +1014,7 @@ static int persist_run(SolveArgs &a, bool mixed, int64_t t, Workspace *w, cfd_so
     inf.rel_residual = fs.relres;
     inf.init_residual = fs.init_relres;
     inf.gamma = fs.gamma;
+    inf.stop_margin = fs.margin;
     inf.seconds = ms * 1e-3;
     if (info) *info = inf;
     if (inf.status != CFD_OK) {
@@ -1001,7 +1059,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.rp = A->rp;
     a.col = A->col;
     a.v32 = A->val32;
-    a.tol = tol * stop_margin(opts);
+    a.tol = tol;
     a.ru_delta = delta;
     a.max_iters = max_iters;
     a.break_at = opts.debug_breakdown_at > 0 ? opts.debug_breakdown_at : -1;
@@ -1043,6 +1101,9 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.partG2 = w->part + 5 * gm;
     a.partFp = w->part + 7 * gm;
     a.partS = w->part + 8 * gm;
+    a.partR = w->part + 9 * gm;
+    a.partRb = w->part + 10 * gm;
+    a.tolv = w->tolv;
     a.S = w->S;
     a.bar = w->bar;
     a.spin_limit = opts.barrier_spins > 0 ? opts.barrier_spins : kBarrierSpins;
@@ -1069,6 +1130,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     }
 
     CFD_HIP(hipEventRecord(w->ev0, s));
+    launch_stop_tol(a, opts, mixed, s);
     if (opts.net) {
         cfd_grid g{A->nx, A->ny, A->nz, A->h};
         rc = net_predict(opts.net, &g, b, w->y, s);
@@ -1158,6 +1220,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     inf.rel_residual = final_state.relres;
     inf.init_residual = final_state.init_relres;
     inf.gamma = final_state.gamma;
+    inf.stop_margin = final_state.margin;
     inf.seconds = ms * 1e-3;
     double tot = 0.0;
     int ns = 0;
@@ -1407,7 +1470,8 @@ struct RbArgs {
     const double *d64;
     const float *d32;
     const int32_t *perm, *iperm;
-    double tol, ru_delta;
+    double ru_delta;
+    const double *tolv;     // [effective tolerance, stopping margin] (see SolveArgs)
     int32_t max_iters;
     int32_t break_at;       // testing: as in SolveArgs
     int32_t G1, G2, Gv;     // red and black sweeps of the iteration, black vector kernels
@@ -1594,7 +1658,7 @@ __device__ inline Decision rb_decide(const RbArgs &a, const CgState &st, double 
         const double nr = sqrt(rr);
         int reason = R_NONE;
         if (!std::isfinite(rr) || !std::isfinite(rz)) reason = R_NONFINITE;
-        else if (nr * st.scale <= a.tol * st.bnorm) reason = R_CONVERGED;
+        else if (nr * st.scale <= a.tolv[0] * st.bnorm) reason = R_CONVERGED;
         else if (MIXED && nr < a.ru_delta * st.rmax) reason = R_REFRESH;
         else if (st.iters >= a.max_iters) reason = R_NOCONV;
         if (reason != R_NONE) {
@@ -1611,7 +1675,10 @@ __device__ inline Decision rb_decide(const RbArgs &a, const CgState &st, double 
         const double rr = reduce_partials(a.partF, a.Gf2, red);
         const double rrp = reduce_partials(a.partFp, a.Gf2, red);
         const double rz = reduce_partials(a.partFz, a.Gf2, red);
-        if (st.mode == MODE_INIT) ns.bnorm = sqrt(reduce_partials(a.partF2, a.Gv, red));
+        if (st.mode == MODE_INIT) {
+            ns.bnorm = sqrt(reduce_partials(a.partF2, a.Gv, red));
+            ns.margin = a.tolv[1];
+        }
         const double tr = sqrt(rr), trp = sqrt(rrp);
         const double bn = ns.bnorm;
         ns.reason = R_NONE;
@@ -1628,7 +1695,7 @@ __device__ inline Decision rb_decide(const RbArgs &a, const CgState &st, double 
         } else {
             ns.relres = trp / bn;
             if (st.mode == MODE_INIT) ns.init_relres = ns.relres;
-            if (trp <= a.tol * bn) {
+            if (trp <= a.tolv[0] * bn) {
                 ns.done = 1;
                 ns.status = CFD_OK;
             } else if (st.reason == R_NOCONV || st.iters >= a.max_iters) {
@@ -2065,6 +2132,10 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     g.partG1 = w->part + 4 * gm;
     g.partG2 = w->part + 5 * gm;
     g.partS = w->part + 8 * gm;
+    g.partR = w->part + 9 * gm;
+    g.partRb = w->part + 10 * gm;
+    g.tolv = w->tolv;
+    g.tol = tol;
 
     RbArgs a{};
     a.n = n;
@@ -2077,7 +2148,7 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     a.d32 = M->d32;
     a.perm = M->perm;
     a.iperm = M->iperm;
-    a.tol = tol * stop_margin(opts);
+    a.tolv = w->tolv;
     a.ru_delta = delta;
     a.max_iters = max_iters;
     a.break_at = opts.debug_breakdown_at > 0 ? opts.debug_breakdown_at : -1;
@@ -2131,6 +2202,7 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     a.S = M->S;
 
     CFD_HIP(hipEventRecord(w->ev0, s));
+    launch_stop_tol(g, opts, mixed, s);
     if (opts.net) {
         cfd_grid gr{A->nx, A->ny, A->nz, A->h};
         rc = net_predict(opts.net, &gr, b, w->y, s);
@@ -2236,6 +2308,7 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
     inf.rel_residual = fs.relres;
     inf.init_residual = fs.init_relres;
     inf.gamma = fs.gamma;
+    inf.stop_margin = fs.margin;
     inf.seconds = ms * 1e-3;
     double tot = 0.0;
     int ns = 0;

@@ -559,6 +559,53 @@ __global__ void sum_partials_kernel(const double *__restrict__ part, int count, 
     if (threadIdx.x == 0) *out = accumulate ? *out + s : s;
 }
 
+// Training pairs (input = b / rms(b), target = (p - mean p) / rms(p - mean p)):
+// partial sums of b^2 and of p (first pass), of (p - mean p)^2 (second pass).
+__global__ void __launch_bounds__(kBlock) pair_sums_kernel(const double *__restrict__ b, const double *__restrict__ p,
+                                                           int64_t n, double *__restrict__ part_bb,
+                                                           double *__restrict__ part_p) {
+    __shared__ double red[kBlock / 64];
+    double bb = 0.0, sp = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        bb = fma(b[i], b[i], bb);
+        sp += p[i];
+    }
+    bb = block_sum(bb, red);
+    sp = block_sum(sp, red);
+    if (threadIdx.x == 0) {
+        part_bb[blockIdx.x] = bb;
+        part_p[blockIdx.x] = sp;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) pair_var_kernel(const double *__restrict__ p, int64_t n,
+                                                          const double *__restrict__ part_p, int count,
+                                                          double *__restrict__ part_pp) {
+    __shared__ double red[kBlock / 64];
+    const double mean = reduce_partials(part_p, count, red) / (double)n;
+    double pp = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        const double d = p[i] - mean;
+        pp = fma(d, d, pp);
+    }
+    pp = block_sum(pp, red);
+    if (threadIdx.x == 0) part_pp[blockIdx.x] = pp;
+}
+
+__global__ void __launch_bounds__(kBlock) pair_write_kernel(const double *__restrict__ b, const double *__restrict__ p,
+                                                            int64_t n, const double *__restrict__ part, int count,
+                                                            float *__restrict__ input, float *__restrict__ target) {
+    __shared__ double red[kBlock / 64];
+    const double sb = sqrt(reduce_partials(part, count, red) / (double)n);
+    const double mean = reduce_partials(part + count, count, red) / (double)n;
+    const double sp = sqrt(reduce_partials(part + 2 * count, count, red) / (double)n);
+    const double ib = sb > 0.0 ? 1.0 / sb : 0.0, ip = sp > 0.0 ? 1.0 / sp : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        input[i] = (float)(b[i] * ib);
+        target[i] = (float)((p[i] - mean) * ip);
+    }
+}
+
 // Adam (Kingma & Ba 2015) on float32 master weights.
 __global__ void adam_kernel(float *__restrict__ th, float *__restrict__ m, float *__restrict__ v,
                             const float *__restrict__ gr, int count, float lr, float b1, float b2, float eps,
@@ -911,6 +958,21 @@ extern "C" int cfd_net_train_step(cfd_net_t N, const cfd_grid *grid, int32_t bat
     CFD_HIP(hipGetLastError());
     N->dirty = true;
     CFD_HIP(hipStreamSynchronize(s));
+    return CFD_OK;
+}
+
+extern "C" int cfd_net_training_pair(cfd_net_t N, const cfd_grid *grid, const double *b, const double *p,
+                                     float *input, float *target, void *stream) {
+    if (!N || !grid || !b || !p || !input || !target) return fail(CFD_EINVAL, "cfd_net_training_pair: null argument");
+    if (grid->nx < 1 || grid->ny < 1 || grid->nz < 1) return fail(CFD_EINVAL, "cfd_net_training_pair: empty grid");
+    const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+    hipStream_t s = (hipStream_t)stream;
+    const int G = std::min(grid1(n), 1024);  // three partial-sum arrays in the 4096-entry scratch
+    double *part = N->part;
+    hipLaunchKernelGGL(pair_sums_kernel, dim3(G), dim3(kBlock), 0, s, b, p, n, part, part + G);
+    hipLaunchKernelGGL(pair_var_kernel, dim3(G), dim3(kBlock), 0, s, p, n, (const double *)(part + G), G, part + 2 * G);
+    hipLaunchKernelGGL(pair_write_kernel, dim3(G), dim3(kBlock), 0, s, b, p, n, (const double *)part, G, input, target);
+    CFD_HIP(hipGetLastError());
     return CFD_OK;
 }
 

@@ -6,15 +6,22 @@ Workload (defaults): 128^3 grid; training pairs from seeded Gaussian-smoothed
 random right-hand sides (sigma = 3 cells) and from lid-driven-cavity time
 steps at Re = 100, 400, 1000, 2000; held-out set of smoothed right-hand sides
 (other seeds) and cavity steps 51..100 at Re = 1000.  Every pair is solved on
-the GPU by FP64 CG to a relative residual of 1e-10.  Input = b / rms(b),
-target = (p - mean p) / rms(b) (the network is bias-free, hence positively
-homogeneous, so this normalisation loses nothing).  Training: Adam on the
-mean squared error, in the library's own bfloat16 matrix-core kernels.
+the GPU by FP64 CG to a relative residual of 1e-10.  The library forms each
+pair (cfd_net_training_pair): input = b / rms(b), target = (p - mean p) /
+rms(p - mean p).  The network is bias-free, hence positively homogeneous, so
+the input scale loses nothing; the solver rescales the prediction by the
+A-optimal factor, so only the target's shape matters, and unit RMS keeps
+every pair's loss at the same scale (a target scaled by rms(b) alone grows
+like the square of the grid size for smooth right-hand sides).  Training:
+Adam on the mean squared error, in the library's own bfloat16 matrix-core
+kernels.
 
-Evaluation: FP64 CG from the network's prediction (scaled by the A-optimal
-factor) against the zero guess on every held-out right-hand side:
-iterations and time.  Prints progress lines and one JSON summary; writes the
-weights (float32 .npy) to --out.
+Evaluation on every held-out right-hand side: the energy-norm ratio
+||x* - gamma y||_A / ||x*||_A of the learned start (gamma the A-optimal
+scale; 1 = no better than the zero guess), and FP64 CG from the learned
+start against the zero guess (iterations and time).  Prints progress lines
+and one JSON summary (also written to --summary); writes the weights
+(float32 .npy) to --out.
 """
 from __future__ import annotations
 
@@ -53,6 +60,7 @@ def main():
     ap.add_argument("--max-train-seconds", type=float, default=1e9)
     ap.add_argument("--init", default=None, help="start from these weights (.npy)")
     ap.add_argument("--out", default=os.path.join(HERE, "weights", "warmstart.npy"))
+    ap.add_argument("--summary", default=os.path.join(HERE, "weights", "warmstart_eval.json"))
     args = ap.parse_args()
 
     import torch
@@ -72,14 +80,17 @@ def main():
         assert info["status"] == 0
         return x
 
+    init = np.load(args.init) if args.init else synth.net_init(args.seed)
+    net = m.Net(init)
+
     def normalise(b, p):
-        r = torch.sqrt(torch.mean(b * b))
-        r = r if float(r) > 0 else torch.ones((), dtype=b.dtype, device=b.device)
-        return (b / r).float(), ((p - p.mean()) / r).float()
+        return net.training_pair(n, b, p)
 
     # ---------------------------------------------------------- training pairs
     X, Y = [], []
     t0 = time.perf_counter()
+    if args.epochs == 0:  # evaluate the initial weights only
+        args.smoothed, args.cavity_steps = 0, 0
     for i in range(args.smoothed):
         b = synth.smoothed_rhs_torch(n, 10000 + i)
         p = solve_pair(b)
@@ -88,7 +99,7 @@ def main():
         Y.append(yi)
         if (i + 1) % 200 == 0:
             log(f"smoothed pairs {i + 1}/{args.smoothed} ({time.perf_counter() - t0:.0f} s)")
-    for re_ in (100, 400, 1000, 2000):
+    for re_ in ((100, 400, 1000, 2000) if args.cavity_steps > 0 else ()):
         nu = 1.0 / re_
         S = m.State(n, nu=nu, lid_u=1.0, keep_rhs=True)
         dt = cavity_dt(n, nu)
@@ -116,8 +127,6 @@ def main():
     log(f"{len(HB)} held-out right-hand sides")
 
     # ---------------------------------------------------------- training
-    init = np.load(args.init) if args.init else synth.net_init(args.seed)
-    net = m.Net(init)
     rng = np.random.default_rng(args.seed)
     xb = torch.empty(args.batch * nv, dtype=torch.float32, device="cuda")
     yb = torch.empty_like(xb)
@@ -150,7 +159,24 @@ def main():
     log(f"weights written to {args.out}")
 
     # ---------------------------------------------------------- evaluation
-    res = {}
+    # energy-norm ratio of the learned start on the pinned system A x* = b:
+    # ||x* - gamma y||_A^2 = b^T x* - (b^T y)^2 / (y^T A y), y[pin] = 0
+    ratios = []
+    for b in HB:
+        xs, info = m.solve(A, b, tol=1e-12, precision="fp64")
+        y = net.forward(n, b)
+        y[0] = 0.0
+        ay = m.spmv(A, y)
+        bx, by, yay = float(torch.dot(b, xs)), float(torch.dot(b, y)), float(torch.dot(y, ay))
+        ratios.append(float(np.sqrt(max(0.0, 1.0 - by * by / (yay * bx)))) if yay > 0 and bx > 0 else 1.0)
+    ratios = np.array(ratios)
+    log(f"energy-norm ratio ||x* - gamma y||_A / ||x*||_A: mean {ratios.mean():.4f}, "
+        f"median {np.median(ratios):.4f}, min {ratios.min():.4f}, max {ratios.max():.4f}")
+    res = {"a_norm_ratio": {"mean": float(ratios.mean()), "median": float(np.median(ratios)),
+                            "min": float(ratios.min()), "max": float(ratios.max()),
+                            "smoothed_mean": float(ratios[:args.heldout_smoothed].mean()),
+                            "cavity_mean": float(ratios[args.heldout_smoothed:].mean())
+                            if len(ratios) > args.heldout_smoothed else None}}
     for form in ("pinned", "projected"):
         it0, it1, t0s, t1s, fb = [], [], [], [], 0
         for b in HB:
@@ -174,7 +200,10 @@ def main():
     summary = {"grid": n, "pairs": npairs, "epochs_run": len(losses), "steps": steps, "batch": args.batch,
                "lr": args.lr, "train_seconds": round(train_s, 1), "loss_first_epoch": losses[0] if losses else None,
                "loss_last_epoch": losses[-1] if losses else None, "heldout": len(HB), "eval": res,
-               "total_seconds": round(time.perf_counter() - t_all, 1)}
+               "total_seconds": round(time.perf_counter() - t_all, 1),
+               "target": "(p - mean p) / rms(p - mean p)", "input": "b / rms(b)"}
+    with open(args.summary, "w") as fh:
+        json.dump(summary, fh, indent=1)
     print(json.dumps(summary), flush=True)
 
 

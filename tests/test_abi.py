@@ -24,7 +24,7 @@ def test_struct_layouts_match_header_sizes():
     # cfd_grid: 3 int32 + pad + double; solve opts/info are 8-byte aligned
     assert ctypes.sizeof(_lib.CfdGrid) == 24
     assert ctypes.sizeof(_lib.CfdSolveOpts) == 64
-    assert ctypes.sizeof(_lib.CfdSolveInfo) == 64
+    assert ctypes.sizeof(_lib.CfdSolveInfo) == 72
 
 
 def test_param_count_is_host_only():

@@ -189,9 +189,15 @@ def test_net_forward_full_size_sampled(lib):
         got.append(y[i + n * (j + n * k)])
     got, want, want64 = np.array(got), np.array(want), np.array(want64)
     # against the network as defined (bfloat16 activations): the GPU differs
-    # by its float32 accumulation, which can move an activation across a
-    # bfloat16 rounding boundary now and then (2.1e-3 measured)
-    assert rel_l2(got, want) <= 5e-3
+    # by its float32 accumulation (relative ~1e-7 at a voxel), which now and
+    # then moves an activation across a bfloat16 rounding boundary (one
+    # bfloat16 ulp, 2^-8, carried through the layers after it): most voxels
+    # agree to float32 rounding, a few (at most 1 in 16) by up to 5 %
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * np.abs(want).max())
+    flipped = rel > 1e-4
+    assert flipped.sum() <= len(pts) // 16, rel[flipped]
+    assert rel.max() <= 5e-2
+    assert rel_l2(got, want) <= 1e-2
     # the bfloat16 storage itself moves these trained weights' output 4.3 %
     # (relative L2) from the float64 network
     assert rel_l2(got, want64) <= 1e-1
@@ -291,13 +297,15 @@ def test_warm_start_solve(lib):
 
 
 def test_trained_warm_start_effect(lib):
-    """The shipped trained weights on held-out smoothed right-hand sides at
-    64^3: the solves from the learned start reach the same answer; the start
-    x0 = gamma*y is never worse than x0 = 0 in the energy norm (gamma is the
-    A-optimal scale), which is what the warm start guarantees; and the
-    iteration counts with and without it are recorded (the measured effect of
-    this network is within a few percent either way, see the training tool's
-    report)."""
+    """What the shipped trained weights gain, on held-out smoothed right-hand
+    sides at 64^3: the start x0 = gamma*y (gamma the A-optimal scale) has a
+    smaller energy-norm error than the zero guess, ||x* - gamma y||_A /
+    ||x*||_A <= 0.97 on each right-hand side (the held-out mean at 128^3 is
+    0.914, weights/warmstart_eval.json); the solves from it reach the same
+    answer; and they take at most 5 % more iterations than from zero (the
+    measured effect on iterations is -0.7 % to -2.8 % at 128^3: the start
+    lowers the error in the modes CG removes within a few iterations anyway,
+    and its residual is larger than b's)."""
     import os
     w = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                      "paper_2504_03697_amd", "weights", "warmstart.npy")
@@ -319,8 +327,8 @@ def test_trained_warm_start_effect(lib):
         Ay = oracle.spmv(ref, y)
         gamma = float(b @ y) / float(y @ Ay)
         e_net = truth - gamma * y
-        e_zero = truth
-        assert float(e_net @ oracle.spmv(ref, e_net)) <= float(e_zero @ oracle.spmv(ref, e_zero)) * (1 + 1e-12)
+        ratio = np.sqrt(float(e_net @ oracle.spmv(ref, e_net)) / float(truth @ oracle.spmv(ref, truth)))
+        assert ratio <= 0.97, ratio
         for prec, form in (("fp64", "pinned"), ("mixed", "projected")):
             x1, i1 = lib.solve(A, bd, net=net, precision=prec, formulation=form)
             x0, i0 = lib.solve(A, bd, precision=prec, formulation=form)
@@ -329,9 +337,8 @@ def test_trained_warm_start_effect(lib):
                 err = np.linalg.norm((x - x.mean()) - (truth - truth.mean())) / np.linalg.norm(truth - truth.mean())
                 assert err <= 1e-9
             assert i1["status"] == 0 and i1["used_fallback"] == 0 and abs(i1["gamma"] - gamma) <= 1e-6 * abs(gamma)
-            rows.append((seed, prec, form, i1["iters"], i0["iters"]))
-            assert i1["iters"] <= 1.1 * i0["iters"] + 2
-    print("learned vs zero start (seed, precision, formulation, iters with net, iters from zero):", rows)
+            rows.append((seed, prec, form, round(ratio, 4), i1["iters"], i0["iters"]))
+            assert i1["iters"] <= 1.05 * i0["iters"]
 
 
 def test_set_params_round_trip(lib):
@@ -349,3 +356,23 @@ def test_set_params_round_trip(lib):
     assert np.array_equal(y1, y2)
     with pytest.raises(lib.CfdError):
         net.set_params(np.zeros(3, dtype=np.float32))
+
+
+@pytest.mark.parametrize("dims", [(17, 9, 13), (32, 32, 32)])
+def test_training_pair_matches_oracle(lib, dims):
+    """cfd_net_training_pair (input b / rms b, target (p - mean p) / rms of
+    that) against the oracle's definition: the float32 results of the same
+    float64 arithmetic up to the order of the float64 sums (a few ulp)."""
+    n = int(np.prod(dims))
+    rng = np.random.default_rng(sum(dims))
+    b = rng.standard_normal(n) * 2.0 + 0.1
+    p = rng.standard_normal(n) * 30.0 + 5.0
+    net = lib.Net(synth.net_init(0))
+    x, t = net.training_pair(dims, torch.from_numpy(b).cuda(), torch.from_numpy(p).cuda())
+    torch.cuda.synchronize()
+    xr, tr = oracle.training_pair(b, p)
+    np.testing.assert_allclose(x.cpu().numpy(), xr, rtol=4 * 2.0**-24, atol=0)
+    np.testing.assert_allclose(t.cpu().numpy(), tr, rtol=4 * 2.0**-24, atol=1e-6 * np.abs(tr).max())
+    z, c = net.training_pair(dims, torch.zeros(n, dtype=torch.float64, device="cuda"),
+                             torch.full((n,), 3.0, dtype=torch.float64, device="cuda"))
+    assert not z.any() and not c.any()

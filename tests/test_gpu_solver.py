@@ -377,14 +377,15 @@ def _white_truth(n, seed):
 def test_mixed_white_noise_pressure_error(lib, n, seed, form, precond):
     """Mixed precision on white-noise (uniform[-1,1]) right-hand sides, whose
     lowest modes hold the least of b, so float32 rounding noise there weighs
-    most: with the default stopping margin (true residual <= 0.05 tol) the
-    pressure is within 1e-9 of an oracle solve at 1e-12 (relative L2, mean
+    most: with the default stopping margin (0.05 tol for a right-hand side
+    whose Rayleigh quotient b^T A b / b^T b exceeds 0.5) the pressure is within 1e-9 of an oracle solve at 1e-12 (relative L2, mean
     removed) and the residual meets tol.  At a residual of 1e-10 itself these
     right-hand sides measured 1.8e-9..3e-8 (128^3)."""
     ref, b, truth = _white_truth(n, seed)
     A = lib.assemble(n, 0)
     x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation=form, precond=precond)
     x = host(x)
+    assert info["stop_margin"] == 0.05  # white noise: Rayleigh quotient ~6
     assert info["status"] == 0 and info["rel_residual"] <= 0.05e-10 * 1.0001
     assert true_relres(ref, b, x) <= 0.05e-10 + relres_rounding(ref, b, x)
     e = mean_removed_err(x, truth)
@@ -394,8 +395,10 @@ def test_mixed_white_noise_pressure_error(lib, n, seed, form, precond):
 
 def test_stop_margin_option(lib):
     """stop_margin sets the residual the solve runs to (tol * margin); 1
-    gives the residual-only stop, more iterations follow a smaller margin,
-    and the float64 default is 1."""
+    gives the residual-only stop, more iterations follow a smaller margin.
+    Defaults: float64 1; mixed 0.05 for a rough right-hand side (white
+    noise, Rayleigh quotient b^T A b / b^T b ~6 > 0.5), 1 for a smooth one
+    (Gaussian-smoothed, ~0.16)."""
     n = 32
     A = lib.assemble(n, 0)
     ref = oracle.assemble(n, 0)
@@ -408,10 +411,24 @@ def test_stop_margin_option(lib):
         assert true_relres(ref, b, host(x)) <= 1e-10 * m + relres_rounding(ref, b, host(x))
         its.append(info["iters"])
     assert its[0] < its[1] < its[2]
-    x, info = lib.solve(A, bd, tol=1e-10, precision="mixed")
-    assert info["iters"] == lib.solve(A, bd, tol=1e-10, precision="mixed", stop_margin=0.05)[1]["iters"]
-    it64 = lib.solve(A, bd, tol=1e-10, precision="fp64")[1]["iters"]
-    assert it64 == lib.solve(A, bd, tol=1e-10, precision="fp64", stop_margin=1.0)[1]["iters"]
+    for drv in ("steps", "persistent"):
+        x, info = lib.solve(A, bd, tol=1e-10, precision="mixed", driver=drv)
+        assert info["stop_margin"] == 0.05
+        assert info["iters"] == lib.solve(A, bd, tol=1e-10, precision="mixed", stop_margin=0.05,
+                                          driver=drv)[1]["iters"]
+        bs = dev(make_rhs((n, n, n), "smoothed", 5))
+        _, i_s = lib.solve(A, bs, tol=1e-10, precision="mixed", driver=drv)
+        assert i_s["stop_margin"] == 1.0
+        assert i_s["iters"] == lib.solve(A, bs, tol=1e-10, precision="mixed", stop_margin=1.0,
+                                         driver=drv)[1]["iters"]
+        for prec in ("fp64", "mixed"):
+            _, i_p = lib.solve(A, bs, tol=1e-10, precision=prec, stop_margin=0.3, driver=drv)
+            assert i_p["stop_margin"] == 0.3 and i_p["rel_residual"] <= 0.3e-10
+    _, i64 = lib.solve(A, bd, tol=1e-10, precision="fp64")
+    assert i64["stop_margin"] == 1.0
+    assert i64["iters"] == lib.solve(A, bd, tol=1e-10, precision="fp64", stop_margin=1.0)[1]["iters"]
+    _, idic = lib.solve(A, bd, tol=1e-10, precision="mixed", precond="dic")
+    assert idic["stop_margin"] == 0.05 and idic["rel_residual"] <= 0.05e-10
 
 
 def test_mixed_cavity_rhs_pressure_error(lib):
@@ -429,10 +446,12 @@ def test_mixed_cavity_rhs_pressure_error(lib):
     ref = oracle.assemble(n, 0)
     truth = oracle.cg(ref, b, tol=1e-12)[0]
     A = lib.assemble(n, 0)
+    bab = float(b @ oracle.spmv(ref, b)) / float(b @ b)
+    assert bab > 0.5  # a rough right-hand side: the stopping margin applies
     for form in ("pinned", "projected"):
         x, info = lib.solve(A, dev(b), tol=1e-10, precision="mixed", formulation=form)
         x = host(x)
-        assert info["status"] == 0
+        assert info["status"] == 0 and info["stop_margin"] == 0.05
         assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
         assert mean_removed_err(x, truth) <= 1e-9, form
 
@@ -633,7 +652,8 @@ def test_persistent_driver_parity(lib, dims, kind, seed, precision, formulation)
     if not np.any(b):
         assert not np.any(x) and info["iters"] == 0
         return
-    stop = tol * (0.05 if precision == "mixed" else 1.0)
+    assert info["stop_margin"] == (0.05 if precision == "mixed" and kind == "uniform" else 1.0)
+    stop = tol * info["stop_margin"]
     assert info["rel_residual"] <= stop
     rr = true_relres(ref, b, x)
     assert rr <= stop + relres_rounding(ref, b, x)

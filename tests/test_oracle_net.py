@@ -126,3 +126,24 @@ def test_round_bf16_definition():
     np.testing.assert_array_equal(r(a), want)
     np.testing.assert_array_equal(r(r(a)), r(a))
 
+
+
+def test_training_pair_definition():
+    """input has unit RMS, target zero mean and unit RMS; both are invariant
+    under positive scaling of b and p, and p + const gives the same target;
+    zero b and constant p give zeros."""
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(1000) * 3.0 + 0.5
+    p = rng.standard_normal(1000) * 40.0 + 7.0
+    x, t = oracle.training_pair(b, p)
+    assert x.dtype == np.float32 and t.dtype == np.float32
+    assert abs(np.sqrt(np.mean(x.astype(np.float64) ** 2)) - 1.0) < 1e-6
+    assert abs(np.mean(t.astype(np.float64))) < 1e-6
+    assert abs(np.sqrt(np.mean(t.astype(np.float64) ** 2)) - 1.0) < 1e-6
+    x2, t2 = oracle.training_pair(5.0 * b, 0.25 * p + 3.0)
+    np.testing.assert_allclose(x2, x, rtol=1e-6)
+    np.testing.assert_allclose(t2, t, rtol=1e-5, atol=1e-6)
+    # ordering is preserved: the target is an increasing affine map of p
+    assert np.all(np.argsort(t, kind="stable") == np.argsort(p, kind="stable"))
+    z, c = oracle.training_pair(np.zeros(10), np.full(10, 2.0))
+    assert not z.any() and not c.any()
