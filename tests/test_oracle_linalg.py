@@ -237,3 +237,48 @@ def test_warm_start_gamma_never_worse():
         assert anorm(xs - g * y) <= anorm(xs) * (1 + 1e-12)
     # exact prediction is recovered exactly
     assert abs(oracle.warm_start_gamma(A, b, 2.0 * xs) - 0.5) < 1e-9
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (3, 5, 2), (6, 4, 5), (1, 7, 3), (8, 8, 8)])
+def test_spectral_solve_matches_dense_solves(dims):
+    """The DCT solver against LAPACK on the Kronecker-sum matrix: the
+    Neumann form's minimum-norm least-squares solution (null space = the
+    constants, so it is the mean-zero one) and the pinned form's unique
+    solution, for pins at a corner, on a face and inside, with b[pin] != 0."""
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    rng = np.random.default_rng(n)
+    L = neumann_3d_dense(nx, ny, nz)
+    c = rng.standard_normal(n)
+    want = np.linalg.lstsq(L, c - c.mean(), rcond=None)[0]
+    got = oracle.neumann_solve_spectral(dims, c)
+    assert np.abs(got - want).max() <= 1e-11 * max(np.abs(want).max(), 1.0)
+    assert abs(got.sum()) <= 1e-11 * n * max(np.abs(want).max(), 1.0)
+    for pin in sorted({0, nx // 2, n - 1, nx // 2 + nx * (ny // 2 + ny * (nz // 2))}):
+        b = rng.standard_normal(n)
+        want = np.linalg.solve(pin_dense(L, pin), b)
+        got = oracle.pinned_solve_spectral(dims, pin, b)
+        assert np.abs(got - want).max() <= 1e-10 * max(np.abs(want).max(), 1.0), pin
+
+
+@pytest.mark.parametrize("n", [4, 16, 64])
+def test_spectral_solve_of_an_eigenvector(n):
+    """The lowest non-constant symmetric mode: L v = 3 * 4 sin^2(pi / (2n)) v."""
+    v = cos_mode(n)
+    lam = 3 * 4 * np.sin(np.pi / (2 * n)) ** 2
+    np.testing.assert_allclose(oracle.neumann_solve_spectral(n, v), v / lam, rtol=0, atol=1e-12 / lam)
+
+
+def test_spectral_solve_agrees_with_cg():
+    """32^3 pinned system, smoothed right-hand side: CG at 1e-13 and the DCT
+    solve agree to within CG's own error bound (cond ~ 1e3 times 1e-13)."""
+    n = 32
+    b = oracle.rhs_prepare(synth.smoothed_rhs(n, 4), 0)
+    A = oracle.assemble(n, 0)
+    x_cg, _, _, st = oracle.cg(A, b, tol=1e-13)
+    assert st == oracle.OK
+    x = oracle.pinned_solve_spectral(n, 0, b)
+    assert x[0] == 0.0
+    assert np.linalg.norm(x - x_cg) <= 1e-9 * np.linalg.norm(x)
+    r = b - oracle.spmv(A, x)
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(b)
