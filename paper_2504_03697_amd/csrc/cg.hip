@@ -233,6 +233,11 @@ double *warm_buffer(cfd_csr_t A) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];  \
     __shared__ __align__(16) VT s_val[kSlabLds];       \
     __shared__ double red[kBlock / 64]
+// The same for a kernel of B threads sweeping tiles of B rows.
+#define CG_SHARED_B(VT, B)                                  \
+    __shared__ __align__(16) int32_t s_col[slab_lds<B>()];  \
+    __shared__ __align__(16) VT s_val[slab_lds<B>()];       \
+    __shared__ double red[(B) / 64]
 
 __device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
@@ -377,7 +382,7 @@ struct Decision {
     double shift;     // projected formulation, final x: + (b_pin - x_pin)
 };
 
-template <bool MIXED>
+template <bool MIXED, int B = kBlock>
 __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double *red) {
     Decision D;
     D.stop = false;
@@ -389,7 +394,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     D.shift = 0.0;
     CgState ns = st;
     if (st.mode == MODE_NORMAL) {
-        const double rr = reduce_partials(a.partB, a.Gb, red);
+        const double rr = reduce_partials<B>(a.partB, a.Gb, red);
         const double nr = sqrt(rr);
         const double thr = a.tolv[0] * st.bnorm;
         int reason = R_NONE;
@@ -410,10 +415,10 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     } else {
         // rr: ||r||^2 of the system being iterated; rrp: ||r||^2 of the pinned
         // system at the (shifted) iterate, which decides convergence
-        const double rr = reduce_partials(a.partF, a.Gf, red);
-        const double rrp = reduce_partials(a.partFp, a.Gf, red);
+        const double rr = reduce_partials<B>(a.partF, a.Gf, red);
+        const double rrp = reduce_partials<B>(a.partFp, a.Gf, red);
         if (st.mode == MODE_INIT) {
-            const double bb = reduce_partials(a.partF2, a.Gf, red);
+            const double bb = reduce_partials<B>(a.partF2, a.Gf, red);
             ns.bnorm = sqrt(bb);
             ns.margin = a.tolv[1];
         } else {
@@ -543,9 +548,10 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
 
 // The solve has ended (mixed): x = 0, or x plus the queued updates, plus the
 // projected formulation's shift.
+template <int B = kBlock>
 __device__ __forceinline__ void a32_final(const SolveArgs &a, const CgState &st, const Decision &D) {
     if (D.zero_x || st.npend > 0 || a.proj)
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * B) {
             a.x[i] = D.zero_x ? 0.0
                    : (a.proj && i == a.pin) ? a.b[a.pin]
                    : folded32(a, st, i) + D.shift;
@@ -556,6 +562,7 @@ __device__ __forceinline__ void a32_final(const SolveArgs &a, const CgState &st,
 // Init/refresh: r = r64 / s_new; p = r + cref p_old; q = A p.  x is written
 // only when the solve ends (queued updates, projected shift); the B steps
 // apply the queue otherwise.
+template <int B = kBlock>
 __device__ __forceinline__ CgState a32_body(const SolveArgs &a, const CgState &st, const Decision &D, double *red,
                                             int32_t *s_col, float *s_val) {
     const float *pold = ring(a, st.pcur);
@@ -570,7 +577,7 @@ __device__ __forceinline__ CgState a32_body(const SolveArgs &a, const CgState &s
     // own row's r and p_old, loaded a tile ahead with the CSR slab (measured
     // 7.6% faster at 256^3 than loading them in the row body)
     auto own = [&](int64_t i) -> float2 { return make_float2(rg(i), use_p ? pold[i] : 0.0f); };
-    csr_sweep_pre<float>(a.rp, a.col, a.v32, a.n, s_col, s_val, own, [&](int64_t i, int rs, int re, float2 o) {
+    csr_sweep_pre<float, B>(a.rp, a.col, a.v32, a.n, s_col, s_val, own, [&](int64_t i, int rs, int re, float2 o) {
         const float acc = neu_fix(a, i, row_product<float>(s_col, s_val, rs, re, wg), wg);
         const float wi = use_p ? fmaf(cf, o.y, o.x) : o.x;
         if (!normal) store_stream(a.r32 + i, o.x);
@@ -578,7 +585,7 @@ __device__ __forceinline__ CgState a32_body(const SolveArgs &a, const CgState &s
         store_stream(a.q32 + i, acc);
         pq = fma((double)wi, (double)acc, pq);
     });
-    pq = block_sum(pq, red);
+    pq = block_sum<B>(pq, red);
     if (threadIdx.x == 0) a.partA[blockIdx.x] = pq;
     CgState ns = D.ns;
     ns.mode = MODE_NORMAL;
@@ -588,23 +595,25 @@ __device__ __forceinline__ CgState a32_body(const SolveArgs &a, const CgState &s
     return ns;
 }
 
-// A kernel, mixed.  The kernel is latency-bound: 8 resident workgroups per CU
-// (the most a SIMD can hold, 64 VGPRs per lane) measured fastest at 256^3.
-__global__ void __launch_bounds__(kBlock, 8) cg_a32(SolveArgs a, int64_t t) {
-    CG_SHARED(float);
+// A kernel, mixed: workgroups of B threads sweeping tiles of B rows.  The
+// kernel is latency-bound: 8 waves per SIMD (64 VGPRs per lane, the most a
+// SIMD holds at that size) measured fastest at 256^3.
+template <int B>
+__global__ void __launch_bounds__(B, 8) cg_a32(SolveArgs a, int64_t t) {
+    CG_SHARED_B(float, B);
     const CgState st = a.S[t & 1];
     CgState *out = &a.S[(t + 1) & 1];
     if (st.done || st.pending) {
         if (lead()) *out = st;
         return;
     }
-    const Decision D = decide<true>(a, st, red);
+    const Decision D = decide<true, B>(a, st, red);
     if (D.stop) {
-        if (D.ns.done) a32_final(a, st, D);
+        if (D.ns.done) a32_final<B>(a, st, D);
         if (lead()) *out = D.ns;
         return;
     }
-    const CgState ns = a32_body(a, st, D, red, s_col, s_val);
+    const CgState ns = a32_body<B>(a, st, D, red, s_col, s_val);
     if (lead()) *out = ns;
 }
 
@@ -960,11 +969,17 @@ int net_predict(cfd_net_t net, const cfd_grid *grid, const double *b, double *y,
 // every workgroup must be resident: a queued one would run its whole tile
 // range after the others finished.
 template <class K>
-static int resident_per_cu(K kernel) {
+static int resident_per_cu(K kernel, int block = kBlock) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb < 1) nb = 1;
     return std::min(nb, 8);
 }
+
+// Rows per tile (and threads per workgroup) of the mixed A kernel.  HBM
+// streams a workgroup's CSR slab faster the more contiguous bytes it spans;
+// at 512 rows (4 workgroups per CU, the same 64 VGPRs per lane as 8 of 256)
+// each slab covers about 14 KB of each of the column and value arrays.
+constexpr int kA32Rows = 512;
 
 struct Grids {
     int a64, f64, a32, f32;
@@ -981,7 +996,7 @@ static const Grids &solver_grids() {
         Grids r;
         r.a64 = std::min(resident_per_cu(cg_a64), kA64PerCu);
         r.f64 = std::min(resident_per_cu(cg_init<false>), resident_per_cu(cg_refresh<false>));
-        r.a32 = resident_per_cu(cg_a32);
+        r.a32 = resident_per_cu(cg_a32<kA32Rows>, kA32Rows);
         r.f32 = std::min(std::min(resident_per_cu(cg_init<true>), resident_per_cu(cg_refresh<true>)),
                          resident_per_cu(warm_gamma));
         return r;
@@ -1064,7 +1079,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     a.max_iters = max_iters;
     a.break_at = opts.debug_breakdown_at > 0 ? opts.debug_breakdown_at : -1;
     const Grids &gr = solver_grids();
-    a.Ga = grid_tiles(A->n, mixed ? gr.a32 : gr.a64);
+    a.Ga = mixed ? grid_tiles(A->n, gr.a32, kA32Rows) : grid_tiles(A->n, gr.a64);
     a.Gb = grid_vec(A->n);
     a.Gf = grid_tiles(A->n, mixed ? gr.f32 : std::min(gr.f64, resident_per_cu(warm_gamma)));
     a.pin = A->pin;
@@ -1170,11 +1185,12 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
             if (time_it) {
                 smp = true;
                 if (mixed)
-                    hipExtLaunchKernelGGL(cg_a32, dim3(a.Ga), dim3(kBlock), 0, s, w->ta[c], w->tb[c], 0, a, t);
+                    hipExtLaunchKernelGGL(cg_a32<kA32Rows>, dim3(a.Ga), dim3(kA32Rows), 0, s, w->ta[c], w->tb[c], 0, a,
+                                          t);
                 else
                     hipExtLaunchKernelGGL(cg_a64, dim3(a.Ga), dim3(kBlock), 0, s, w->ta[c], w->tb[c], 0, a, t);
             } else if (mixed) {
-                hipLaunchKernelGGL(cg_a32, dim3(a.Ga), dim3(kBlock), 0, s, a, t);
+                hipLaunchKernelGGL(cg_a32<kA32Rows>, dim3(a.Ga), dim3(kA32Rows), 0, s, a, t);
             } else {
                 hipLaunchKernelGGL(cg_a64, dim3(a.Ga), dim3(kBlock), 0, s, a, t);
             }

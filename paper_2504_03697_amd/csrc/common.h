@@ -29,6 +29,9 @@ constexpr int kTileRows = 256;   // CSR rows per SpMV tile: one row per thread
 constexpr int kMaxRowNnz = 7;    // the 7-point stencil
 constexpr int kXcd = 8;          // MI355X: 8 accelerator complex dies, each with its own L2
 constexpr int kSlab = kTileRows * kMaxRowNnz + 4;  // entries a slab may span (+ alignment slack)
+// The same for a tile of B rows (SpMV-shaped kernels of B threads, one row each).
+template <int B>
+constexpr int slab_entries() { return B * kMaxRowNnz + 4; }
 constexpr int kPad = 8;          // extra CSR entries allocated past nnz (vector over-read)
 
 struct Device {
@@ -40,7 +43,7 @@ int device_info(Device *d);
 // Grid sizes for the solver's kernels on this device (fixed per device so
 // reductions, which depend on the number of partial sums, are reproducible).
 int grid_spmv(int64_t n, bool fp64_vectors);  // the standalone SpMV
-int grid_tiles(int64_t n, int per_cu);  // SpMV-shaped grid with per_cu workgroups per CU
+int grid_tiles(int64_t n, int per_cu, int tile_rows = kTileRows);  // SpMV-shaped grid, per_cu workgroups per CU
 int grid_vec(int64_t n);
 
 // ---------------------------------------------------------------- matrix handle
@@ -102,8 +105,9 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Sum over the workgroup in a fixed order; every thread receives the same
-// bits.  `red` must be __shared__ double[kBlock / 64].
+// Sum over the workgroup of B threads in a fixed order; every thread
+// receives the same bits.  `red` must be __shared__ double[B / 64].
+template <int B = kBlock>
 __device__ inline double block_sum(double v, double *red) {
     v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -111,28 +115,29 @@ __device__ inline double block_sum(double v, double *red) {
     __syncthreads();
     double s = 0.0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+    for (int w = 0; w < B / 64; ++w) s += red[w];
     __syncthreads();
     return s;
 }
 
 // Reduce count partial sums written by the previous kernel, in a fixed order
-// (thread t sums entries t, t+256, ... serially, then block_sum).  Every
+// (thread t sums entries t, t+B, ... serially, then block_sum).  Every
 // block of the calling kernel obtains the same bits.
+template <int B = kBlock>
 __device__ inline double reduce_partials(const double *part, int count, double *red) {
     // eight loads in flight, then the adds in the same order as one at a time
     // (every kernel starts with this reduction: 0.6 % off the mixed SpMV kernel)
     double s = 0.0;
     int i = threadIdx.x;
-    for (; i + 7 * kBlock < count; i += 8 * kBlock) {
+    for (; i + 7 * B < count; i += 8 * B) {
         double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = part[i + k * kBlock];
+        for (int k = 0; k < 8; ++k) v[k] = part[i + k * B];
 #pragma unroll
         for (int k = 0; k < 8; ++k) s += v[k];
     }
-    for (; i < count; i += kBlock) s += part[i];
-    return block_sum(s, red);
+    for (; i < count; i += B) s += part[i];
+    return block_sum<B>(s, red);
 }
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -148,19 +153,21 @@ __device__ inline void store_stream(T *p, T v) {
     __builtin_nontemporal_store(v, p);
 }
 
-// Software-pipelined CSR slab loader.  A tile is kTileRows consecutive rows;
+// Software-pipelined CSR slab loader.  A tile is B consecutive rows (B the
+// workgroup size);
 // its slab is the contiguous range [ea, e1) of the column and value arrays
 // (ea = row_ptr[r0] rounded down to a multiple of 4, so every load is a
 // 16-byte vector load).  fetch() issues the loads of a tile into registers;
 // commit() stores them to LDS.  The sweep below fetches tile t+1 while the
 // rows of tile t gather their vector entries, which keeps HBM requests in
 // flight across the whole tile loop.
-template <class VT>
+template <class VT, int B = kBlock>
 struct SlabPipe {
     typedef typename std::conditional<sizeof(VT) == 8, f64x2, f32x4>::type VV;
     static constexpr int kPerV = sizeof(VV) / sizeof(VT);  // values per vector load
-    static constexpr int kVecC = (kSlab + 4 * kBlock - 1) / (4 * kBlock);
-    static constexpr int kVecV = (kSlab + kPerV * kBlock - 1) / (kPerV * kBlock);
+    static constexpr int kS = slab_entries<B>();
+    static constexpr int kVecC = (kS + 4 * B - 1) / (4 * B);
+    static constexpr int kVecV = (kS + kPerV * B - 1) / (kPerV * B);
     i32x4 rc[kVecC];
     VV rv[kVecV];
     int64_t r0 = 0;
@@ -169,8 +176,8 @@ struct SlabPipe {
     __device__ inline void fetch(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                  const VT *__restrict__ val, int64_t n, int64_t tile) {
         const int tid = threadIdx.x;
-        r0 = tile * kTileRows;
-        nr = (int)(n - r0 < kTileRows ? n - r0 : kTileRows);
+        r0 = tile * B;
+        nr = (int)(n - r0 < B ? n - r0 : B);
         const int32_t e0 = rp[r0], e1 = rp[r0 + nr];
         ea = e0 & ~3;
         cnt = e1 - ea;
@@ -178,10 +185,10 @@ struct SlabPipe {
         const VV *v4 = reinterpret_cast<const VV *>(val + ea);
 #pragma unroll
         for (int v = 0; v < kVecC; ++v)
-            if ((tid + v * kBlock) * 4 < cnt) rc[v] = __builtin_nontemporal_load(c4 + tid + v * kBlock);
+            if ((tid + v * B) * 4 < cnt) rc[v] = __builtin_nontemporal_load(c4 + tid + v * B);
 #pragma unroll
         for (int v = 0; v < kVecV; ++v)
-            if ((tid + v * kBlock) * kPerV < cnt) rv[v] = __builtin_nontemporal_load(v4 + tid + v * kBlock);
+            if ((tid + v * B) * kPerV < cnt) rv[v] = __builtin_nontemporal_load(v4 + tid + v * B);
         if (tid < nr) {
             rs = rp[r0 + tid] - ea;
             re = rp[r0 + tid + 1] - ea;
@@ -203,10 +210,10 @@ struct SlabPipe {
         const VV *v4 = reinterpret_cast<const VV *>(val + ea);
 #pragma unroll
         for (int v = 0; v < kVecC; ++v)
-            if ((tid + v * kBlock) * 4 < cnt) rc[v] = __builtin_nontemporal_load(c4 + tid + v * kBlock);
+            if ((tid + v * B) * 4 < cnt) rc[v] = __builtin_nontemporal_load(c4 + tid + v * B);
 #pragma unroll
         for (int v = 0; v < kVecV; ++v)
-            if ((tid + v * kBlock) * kPerV < cnt) rv[v] = __builtin_nontemporal_load(v4 + tid + v * kBlock);
+            if ((tid + v * B) * kPerV < cnt) rv[v] = __builtin_nontemporal_load(v4 + tid + v * B);
         if (tid < nr) {
             rs = rp[r0 + tid] - ea;
             re = rp[r0 + tid + 1] - ea;
@@ -219,27 +226,29 @@ struct SlabPipe {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int v = 0; v < kVecC; ++v)
-            if ((tid + v * kBlock) * 4 < cnt) reinterpret_cast<i32x4 *>(s_col)[tid + v * kBlock] = rc[v];
+            if ((tid + v * B) * 4 < cnt) reinterpret_cast<i32x4 *>(s_col)[tid + v * B] = rc[v];
 #pragma unroll
         for (int v = 0; v < kVecV; ++v)
-            if ((tid + v * kBlock) * kPerV < cnt) reinterpret_cast<VV *>(s_val)[tid + v * kBlock] = rv[v];
+            if ((tid + v * B) * kPerV < cnt) reinterpret_cast<VV *>(s_val)[tid + v * B] = rv[v];
     }
 };
 
 // LDS entries reserved per slab: commit() stores whole vectors only below cnt
 // (at most kSlab + 3 entries).
 constexpr int kSlabLds = kSlab + 4;
+template <int B>
+constexpr int slab_lds() { return slab_entries<B>() + 4; }
 
 // Sweep the tiles assigned to this workgroup (XCD-aware schedule).  For each
 // tile, once its slab is in LDS, body(i, rs, re) runs for every row i of the
 // tile owned by this thread (one row per thread), with [rs, re) the row's
 // entries in s_col/s_val.  The call is workgroup-uniform.
-template <class VT, class Body>
+template <class VT, int B = kBlock, class Body>
 __device__ inline void csr_sweep(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                  const VT *__restrict__ val, int64_t n, int32_t *s_col, VT *s_val, Body &&body) {
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    const int64_t ntiles = (n + B - 1) / B;
     const TileRange tr = tile_range(ntiles);
-    SlabPipe<VT> P;
+    SlabPipe<VT, B> P;
     if (tr.first < tr.end) P.fetch(rp, col, val, n, tr.first);
     for (int64_t t = tr.first; t < tr.end; t += tr.step) {
         const int64_t r0 = P.r0;
@@ -255,14 +264,14 @@ __device__ inline void csr_sweep(const int32_t *__restrict__ rp, const int32_t *
 // csr_sweep with per-row operands fetched one tile ahead as well: pre(i)
 // loads what the body needs from row i's own vector entries, for the next
 // tile while the current one computes; body(i, rs, re, v) gets the value.
-template <class VT, class Pre, class Body>
+template <class VT, int B = kBlock, class Pre, class Body>
 __device__ inline void csr_sweep_pre(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                      const VT *__restrict__ val, int64_t n, int32_t *s_col, VT *s_val, Pre &&pre,
                                      Body &&body) {
     using T = decltype(pre(int64_t(0)));
-    const int64_t ntiles = (n + kTileRows - 1) / kTileRows;
+    const int64_t ntiles = (n + B - 1) / B;
     const TileRange tr = tile_range(ntiles);
-    SlabPipe<VT> P;
+    SlabPipe<VT, B> P;
     T next{};
     if (tr.first < tr.end) {
         P.fetch(rp, col, val, n, tr.first);
@@ -308,12 +317,13 @@ __device__ inline Acc row_product(const int32_t *s_col, const VT *s_val, int rs,
 // float32 SpMV, the red-black sweeps and the float64 CG kernel gain from it
 // (3-4 % at 256^3); the mixed CG kernel (at its 64-register limit) and the
 // float64 SpMV do not, and keep SlabPipe.
-template <class VT>
+template <class VT, int B = kBlock>
 struct SlabStream {
     typedef typename std::conditional<sizeof(VT) == 8, f64x2, f32x4>::type VV;
     static constexpr int kPerV = sizeof(VV) / sizeof(VT);  // values per vector load
-    static constexpr int kVecC = (kSlab + 4 * kBlock - 1) / (4 * kBlock);
-    static constexpr int kVecV = (kSlab + kPerV * kBlock - 1) / (kPerV * kBlock);
+    static constexpr int kS = slab_entries<B>();
+    static constexpr int kVecC = (kS + 4 * B - 1) / (4 * B);
+    static constexpr int kVecV = (kS + kPerV * B - 1) / (kPerV * B);
     i32x4 rc[kVecC];
     VV rv[kVecV];
     int64_t r0 = 0;
@@ -336,9 +346,9 @@ struct SlabStream {
         const i32x4 *c4 = reinterpret_cast<const i32x4 *>(col + ea);
         const VV *v4 = reinterpret_cast<const VV *>(val + ea);
 #pragma unroll
-        for (int v = 0; v < kVecC; ++v) rc[v] = __builtin_nontemporal_load(c4 + min(tid + v * kBlock, lastc));
+        for (int v = 0; v < kVecC; ++v) rc[v] = __builtin_nontemporal_load(c4 + min(tid + v * B, lastc));
 #pragma unroll
-        for (int v = 0; v < kVecV; ++v) rv[v] = __builtin_nontemporal_load(v4 + min(tid + v * kBlock, lastv));
+        for (int v = 0; v < kVecV; ++v) rv[v] = __builtin_nontemporal_load(v4 + min(tid + v * B, lastv));
         const int64_t rr = r0 + min(tid, nr - 1);
         rsr = rp[rr];
         rer = rp[rr + 1];
@@ -355,14 +365,14 @@ struct SlabStream {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int v = 0; v < kVecC; ++v)
-            if ((tid + v * kBlock) * 4 < cnt) reinterpret_cast<i32x4 *>(s_col)[tid + v * kBlock] = rc[v];
+            if ((tid + v * B) * 4 < cnt) reinterpret_cast<i32x4 *>(s_col)[tid + v * B] = rc[v];
 #pragma unroll
         for (int v = 0; v < kVecV; ++v)
-            if ((tid + v * kBlock) * kPerV < cnt) reinterpret_cast<VV *>(s_val)[tid + v * kBlock] = rv[v];
+            if ((tid + v * B) * kPerV < cnt) reinterpret_cast<VV *>(s_val)[tid + v * B] = rv[v];
     }
 };
 
-// Sweep the rows [row_begin, row_end) in tiles of kTileRows rows counted from
+// Sweep the rows [row_begin, row_end) in tiles of B rows counted from
 // row_begin, the tiles assigned to this workgroup by the XCD-aware schedule.
 // pre(i) loads what the body needs from row i's own vector entries; it runs
 // for the next tile while the current one computes (it must accept any row
@@ -371,21 +381,21 @@ struct SlabStream {
 // owned by this thread (one row per thread), with [rs, re) the row's entries
 // in s_col/s_val and v = pre(i).  The call is workgroup-uniform; every row
 // holds at least one entry.
-template <class VT, class Pre, class Body>
+template <class VT, int B = kBlock, class Pre, class Body>
 __device__ inline void csr_stream_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                       const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
                                       int32_t *s_col, VT *s_val, Pre &&pre, Body &&body) {
     using T = decltype(pre(int64_t(0)));
     const int64_t rows = row_end - row_begin;
-    const int64_t ntiles = (rows + kTileRows - 1) / kTileRows;
+    const int64_t ntiles = (rows + B - 1) / B;
     const TileRange tr = tile_range(ntiles);
     if (tr.first >= tr.end) return;
-    auto tile_r0 = [&](int64_t t) -> int64_t { return row_begin + t * kTileRows; };
+    auto tile_r0 = [&](int64_t t) -> int64_t { return row_begin + t * B; };
     auto tile_nr = [&](int64_t t) -> int {
-        return (int)(rows - t * kTileRows < kTileRows ? rows - t * kTileRows : kTileRows);
+        return (int)(rows - t * B < B ? rows - t * B : B);
     };
     const int tid = threadIdx.x;
-    SlabStream<VT> P;
+    SlabStream<VT, B> P;
     {
         const int64_t t = tr.first, tq = t + tr.step < tr.end ? t + tr.step : t;
         const int64_t r0 = tile_r0(t);
