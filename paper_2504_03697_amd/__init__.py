@@ -139,7 +139,7 @@ def rhs_prepare_noalloc(A: Csr, b):
     return b
 
 
-DRIVER = {"auto": 0, "steps": 1, "persistent": 2}
+DRIVER = {"auto": 0, "steps": 1, "persistent": 2, "resident": 3}
 
 
 def solve_opts(precision="fp64", max_iters=0, ru_delta=0.0, net=None, chunk=0, timing=False, formulation="pinned",

@@ -382,8 +382,12 @@ struct Decision {
     double shift;     // projected formulation, final x: + (b_pin - x_pin)
 };
 
-template <bool MIXED, int B = kBlock>
-__device__ inline Decision decide(const SolveArgs &a, const CgState &st, double *red) {
+// The decision from the reduced sums: rr = ||r||^2 (normal mode: the
+// recursive residual); after cg_init or a refresh also rrp (the pinned
+// system's ||r||^2) and, after cg_init, bb = ||b||^2.
+template <bool MIXED>
+__device__ inline Decision decide_core(const SolveArgs &a, const CgState &st, double rr_in, double rrp_in,
+                                       double bb_in) {
     Decision D;
     D.stop = false;
     D.zero_x = false;
@@ -394,7 +398,7 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     D.shift = 0.0;
     CgState ns = st;
     if (st.mode == MODE_NORMAL) {
-        const double rr = reduce_partials<B>(a.partB, a.Gb, red);
+        const double rr = rr_in;
         const double nr = sqrt(rr);
         const double thr = a.tolv[0] * st.bnorm;
         int reason = R_NONE;
@@ -415,11 +419,9 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     } else {
         // rr: ||r||^2 of the system being iterated; rrp: ||r||^2 of the pinned
         // system at the (shifted) iterate, which decides convergence
-        const double rr = reduce_partials<B>(a.partF, a.Gf, red);
-        const double rrp = reduce_partials<B>(a.partFp, a.Gf, red);
+        const double rr = rr_in, rrp = rrp_in;
         if (st.mode == MODE_INIT) {
-            const double bb = reduce_partials<B>(a.partF2, a.Gf, red);
-            ns.bnorm = sqrt(bb);
+            ns.bnorm = sqrt(bb_in);
             ns.margin = a.tolv[1];
         } else {
             D.fold = true;  // refresh (float64 path): this A kernel folds x += alpha p
@@ -474,6 +476,17 @@ __device__ inline Decision decide(const SolveArgs &a, const CgState &st, double 
     }
     D.ns = ns;
     return D;
+}
+
+// The decision at the start of an A step, from the partial sums the
+// previous step left (identical in every workgroup).
+template <bool MIXED, int B = kBlock>
+__device__ inline Decision decide(const SolveArgs &a, const CgState &st, double *red) {
+    if (st.mode == MODE_NORMAL) return decide_core<MIXED>(a, st, reduce_partials<B>(a.partB, a.Gb, red), 0.0, 0.0);
+    const double rr = reduce_partials<B>(a.partF, a.Gf, red);
+    const double rrp = reduce_partials<B>(a.partFp, a.Gf, red);
+    const double bb = st.mode == MODE_INIT ? reduce_partials<B>(a.partF2, a.Gf, red) : 0.0;
+    return decide_core<MIXED>(a, st, rr, rrp, bb);
 }
 
 // Bodies of the solver's kernels, shared by the launch-per-step driver (one
@@ -879,6 +892,238 @@ __global__ void __launch_bounds__(kBlock) cg_persist(SolveArgs a, int64_t t) {
     if (lead()) a.S[(t + 1) & 1] = st;
 }
 
+// ---------------------------------------------------------------- resident driver
+//
+// Float64, small grids (up to kResMaxRows cells): one workgroup runs the
+// whole solve after cg_init, with no grid barrier and no global round trip
+// per step.  Thread t owns rows t, t + kResThreads, ...: their columns (as
+// 16-bit offsets from the row, |col - i| < n <= kResMaxRows), x, r and q
+// stay in its registers, the matrix values in LDS, and the direction (or x
+// during a refresh) in LDS, where the row products gather it.  Thread 0 holds the control state in LDS and takes each
+// decision with decide_core, the launch-per-step driver's rules; the
+// per-row arithmetic is that driver's too.  The sums are reduced over one
+// workgroup instead of per-workgroup partial sums, and x takes each step
+// x += alpha p at once rather than at the next A step (the same fma).
+constexpr int kResThreads = 1024;
+constexpr int kResRows = 4;
+constexpr int64_t kResMaxRows = (int64_t)kResThreads * kResRows;
+
+enum ResOp : int32_t { OP_END = 0, OP_REFRESH = 1, OP_STEP = 2, OP_FINAL = 3 };
+
+struct ResCtl {
+    CgState st;
+    double beta, shift, alpha;
+    int32_t op, normal, zero_x, update;
+};
+
+// Thread 0: the next operation from the control state and the latest sums.
+// Not inlined: the decision's temporaries then take call-clobbered
+// registers instead of competing with the rows each thread keeps.  The
+// arguments are the fields of SolveArgs that the decision reads.
+__device__ __noinline__ void res_control(double *tolv, double ru_delta, int32_t max_iters, int32_t proj,
+                                         double bpin, ResCtl *cp, double rr, double rrp, double bb) {
+    SolveArgs a{};
+    a.tolv = tolv;
+    a.ru_delta = ru_delta;
+    a.max_iters = max_iters;
+    a.proj = proj;
+    a.b = &bpin;
+    a.pin = 0;
+    ResCtl &c = *cp;
+    for (;;) {
+        if (c.st.done) {
+            c.op = OP_END;
+            return;
+        }
+        if (c.st.pending) {
+            c.op = OP_REFRESH;
+            return;
+        }
+        const Decision D = decide_core<false>(a, c.st, rr, rrp, bb);
+        if (D.stop) {
+            c.st = D.ns;
+            if (D.ns.done) {
+                c.op = OP_FINAL;
+                c.zero_x = D.zero_x;
+                c.shift = D.shift;
+                return;
+            }
+            continue;  // a refresh is pending
+        }
+        c.op = OP_STEP;
+        c.beta = D.beta;
+        c.normal = c.st.mode == MODE_NORMAL;
+        c.st = D.ns;
+        return;
+    }
+}
+
+// f(integral_constant<int, k>) for k = 0 .. K-1: the row slot is a
+// compile-time index, so the per-row arrays stay in registers.
+template <int K, class F>
+__device__ __forceinline__ void res_for(F &&f) {
+    if constexpr (K > 0) {
+        res_for<K - 1>(f);
+        f(std::integral_constant<int, K - 1>{});
+    }
+}
+
+__global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t t) {
+    __shared__ float s_val[kResRows * kMaxRowNnz * kResThreads];  // [row slot][entry][thread]
+    __shared__ double s_v[kResMaxRows];
+    __shared__ double red[kResThreads / 64];
+    __shared__ ResCtl ctl;
+    const int tid = threadIdx.x;
+    const int64_t n = a.n;
+    constexpr int kPacked = (kMaxRowNnz + 1) / 2;
+    uint32_t cc[kResRows][kPacked];  // two 16-bit column offsets per word
+    // per row slot k, 4 bits at 4k: the row length (0..7), and bit 3 set for
+    // the rows the projected formulation corrects (the pin and its neighbours)
+    uint32_t meta = 0u;
+    double x[kResRows], r[kResRows], q[kResRows];
+    auto row = [&](auto kc) -> int64_t { return tid + (int64_t)decltype(kc)::value * kResThreads; };
+    res_for<kResRows>([&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        const int64_t i = row(kc);
+        const bool own = i < n;
+        const int32_t e0 = own ? a.rp[i] : 0;
+        const int len = own ? a.rp[i + 1] - e0 : 0;
+        const bool fix = own && a.proj && (i == a.pin || is_pin_nb(a, i));
+        meta |= ((uint32_t)len | (fix ? 8u : 0u)) << (4 * k);
+#pragma unroll
+        for (int w = 0; w < kPacked; ++w) cc[k][w] = 0u;
+#pragma unroll
+        for (int e = 0; e < kMaxRowNnz; ++e) {
+            const int32_t off = e < len ? a.col[e0 + e] - (int32_t)i : 0;
+            cc[k][e / 2] |= ((uint32_t)off & 0xffffu) << (16 * (e & 1));
+            s_val[(k * kMaxRowNnz + e) * kResThreads + tid] = e < len ? a.v32[e0 + e] : 0.0f;
+        }
+        x[k] = own ? a.x[i] : 0.0;
+        r[k] = own ? a.r[i] : 0.0;
+        q[k] = 0.0;
+    });
+    // row k of A (A_neu in the projected formulation) times the vector in s_v
+    auto sv = [&](int32_t j) -> double { return s_v[j]; };
+    auto rowprod = [&](auto kc) -> double {
+        constexpr int k = decltype(kc)::value;
+        const int32_t i = (int32_t)row(kc);
+        const uint32_t m = (meta >> (4 * k)) & 15u;
+        const int len = (int)(m & 7u);
+        double acc = 0.0;
+#pragma unroll
+        for (int e = 0; e < kMaxRowNnz; ++e)
+            if (e < len) {
+                const int32_t j = i + (int32_t)(int16_t)(cc[k][e / 2] >> (16 * (e & 1)));
+                acc = fma((double)s_val[(k * kMaxRowNnz + e) * kResThreads + tid], s_v[j], acc);
+            }
+        return (m & 8u) ? neu_fix(a, (int64_t)i, acc, sv) : acc;
+    };
+    // the first decision reduces the partial sums cg_init left
+    if (tid == 0) ctl.st = a.S[t & 1];
+    __syncthreads();
+    double rr = 0.0, rrp = 0.0, bb = 0.0;
+    if (!ctl.st.done && !ctl.st.pending) {
+        if (ctl.st.mode == MODE_NORMAL) {
+            rr = reduce_partials<kResThreads>(a.partB, a.Gb, red);
+        } else {
+            rr = reduce_partials<kResThreads>(a.partF, a.Gf, red);
+            rrp = reduce_partials<kResThreads>(a.partFp, a.Gf, red);
+            if (ctl.st.mode == MODE_INIT) bb = reduce_partials<kResThreads>(a.partF2, a.Gf, red);
+        }
+    }
+    const double bpin = a.proj ? a.b[a.pin] : 0.0;
+    for (;;) {
+        if (tid == 0) res_control(a.tolv, a.ru_delta, a.max_iters, a.proj, bpin, &ctl, rr, rrp, bb);
+        __syncthreads();
+        const int32_t op = ctl.op;
+        if (op == OP_END) break;
+        if (op == OP_FINAL) {
+            const bool zx = ctl.zero_x;
+            const double sh = ctl.shift;
+            res_for<kResRows>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const int64_t i = row(kc);
+                if (i < n) a.x[i] = zx ? 0.0 : (a.proj && i == a.pin) ? a.b[a.pin] : x[k] + sh;
+            });
+            break;
+        }
+        // Refresh: r = c - A x at the current iterate (x gathered from s_v).
+        // A step: p = r + beta p_old (after a restart p = r) into s_v; q = A p.
+        const bool refresh = op == OP_REFRESH;
+        const bool normal = ctl.normal != 0;
+        const double beta = ctl.beta;
+        res_for<kResRows>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int64_t i = row(kc);
+            if (i < n) s_v[i] = refresh ? x[k] : normal ? fma(beta, s_v[i], r[k]) : r[k];
+        });
+        __syncthreads();
+        double s1 = 0.0, s2 = 0.0;
+        res_for<kResRows>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const int64_t i = row(kc);
+            if (i < n) {
+                const double prod = rowprod(kc);
+                if (refresh) {
+                    const double ri = a.c[i] - prod;
+                    r[k] = ri;
+                    s1 = fma(ri, ri, s1);
+                    if (!(a.proj && i == a.pin)) s2 = fma(ri, ri, s2);
+                } else {
+                    q[k] = prod;
+                    s1 = fma(s_v[i], prod, s1);  // p^T q
+                }
+            }
+        });
+        if (refresh) {
+            const double xpin = s_v[a.pin];
+            rr = block_sum<kResThreads>(s1, red);
+            rrp = block_sum<kResThreads>(s2, red);
+            bb = 0.0;
+            if (tid == 0) {
+                ctl.st.pending = 0;
+                ctl.st.mode = MODE_REFRESH;
+                ctl.st.updates += 1;
+                ctl.st.xpin = xpin;
+            }
+            continue;
+        }
+        const double pq = block_sum<kResThreads>(s1, red);
+        // B step: alpha = rho / p^T q; x += alpha p; r -= alpha q; ||r||^2
+        if (tid == 0) {
+            ctl.st.mode = MODE_NORMAL;
+            ctl.st.iters += 1;
+            ctl.st.alpha = 0.0;
+            const double alpha = ctl.st.rho / pq;
+            if (!(pq > 0.0) || !std::isfinite(alpha) || ctl.st.iters == a.break_at) {
+                ctl.st.pending = 1;
+                ctl.st.reason = R_BREAKDOWN;
+                ctl.update = 0;
+            } else {
+                ctl.update = 1;
+                ctl.alpha = alpha;
+            }
+        }
+        __syncthreads();
+        if (ctl.update) {
+            const double alpha = ctl.alpha;
+            double s1 = 0.0;
+            res_for<kResRows>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const int64_t i = row(kc);
+                if (i < n) {
+                    x[k] = fma(alpha, s_v[i], x[k]);  // s_v still holds p
+                    r[k] = fma(-alpha, q[k], r[k]);
+                    s1 = fma(r[k], r[k], s1);
+                }
+            });
+            rr = block_sum<kResThreads>(s1, red);
+        }
+        rrp = bb = 0.0;
+    }
+    if (tid == 0) a.S[(t + 1) & 1] = ctl.st;
+}
+
 // Warm start: partial sums of y^T A y and c^T y for gamma, with y[pin] = 0
 // (then y^T A_neu y = y^T A_pin y, and c^T y = b^T y - b_pin * sum of y over
 // the pin's neighbours in the projected formulation).
@@ -1011,10 +1256,23 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
 
 // Run the persistent driver after cg_init (launch sequence number t) and
 // fill info.  The whole solve is one launch, so no per-launch timings.
+// Run the resident driver after cg_init and fill info the same way.
+static int finish_single_launch(int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s);
+
+static int resident_run(SolveArgs &a, int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s) {
+    hipLaunchKernelGGL(cg_resident, dim3(1), dim3(kResThreads), 0, s, a, t);
+    CFD_HIP(hipGetLastError());
+    return finish_single_launch(t, w, info, s);
+}
+
 static int persist_run(SolveArgs &a, bool mixed, int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s) {
     void *args[] = {(void *)&a, (void *)&t};
     const void *kern = mixed ? (const void *)cg_persist<true> : (const void *)cg_persist<false>;
     CFD_HIP(hipLaunchCooperativeKernel(kern, dim3(a.Ga), dim3(kBlock), args, 0, s));
+    return finish_single_launch(t, w, info, s);
+}
+
+static int finish_single_launch(int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s) {
     CFD_HIP(hipMemcpyAsync(&w->host[0], &w->S[(t + 1) & 1], sizeof(CgState), hipMemcpyDeviceToHost, s));
     CFD_HIP(hipEventRecord(w->ev1, s));
     CFD_HIP(hipEventSynchronize(w->ev1));
@@ -1036,7 +1294,7 @@ static int persist_run(SolveArgs &a, bool mixed, int64_t t, Workspace *w, cfd_so
         const char *what = inf.status == CFD_ENOCONV ? "max_iters reached"
                          : inf.status == CFD_EBREAKDOWN ? "breakdown: p^T A p <= 0"
                          : inf.status == CFD_ENONFINITE ? "non-finite value in the solve"
-                         : inf.status == CFD_EHIP ? "persistent driver: a grid barrier wait timed out"
+                         : inf.status == CFD_EHIP ? "single-launch driver: a grid barrier wait timed out"
                                                   : "solver error";
         return fail(inf.status, std::string("cfd_solve: ") + what);
     }
@@ -1125,9 +1383,16 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
 
     // Driver: one cooperative launch for the whole iteration (small grids,
     // where launches set the pace), or one launch per step.
-    if (opts.driver != CFD_DRIVER_AUTO && opts.driver != CFD_DRIVER_STEPS && opts.driver != CFD_DRIVER_PERSISTENT)
+    if (opts.driver != CFD_DRIVER_AUTO && opts.driver != CFD_DRIVER_STEPS && opts.driver != CFD_DRIVER_PERSISTENT &&
+        opts.driver != CFD_DRIVER_RESIDENT)
         return fail(CFD_EINVAL, "cfd_solve: unknown driver");
-    bool persist = opts.driver == CFD_DRIVER_PERSISTENT || (opts.driver == CFD_DRIVER_AUTO && A->n <= kPersistMaxRows);
+    if (opts.driver == CFD_DRIVER_RESIDENT && (mixed || A->n > kResMaxRows))
+        return fail(CFD_EINVAL, "cfd_solve: the resident driver takes float64 solves of at most " +
+                                    std::to_string(kResMaxRows) + " cells");
+    const bool resident = opts.driver == CFD_DRIVER_RESIDENT ||
+                          (opts.driver == CFD_DRIVER_AUTO && !mixed && A->n <= kResMaxRows);
+    bool persist = !resident && (opts.driver == CFD_DRIVER_PERSISTENT ||
+                                 (opts.driver == CFD_DRIVER_AUTO && A->n <= kPersistMaxRows));
     if (persist) {
         int coop = 0;
         CFD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, A->device));
@@ -1159,6 +1424,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     else hipLaunchKernelGGL(cg_init<false>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
     ++t;
     CFD_HIP(hipGetLastError());
+    if (resident) return resident_run(a, t, w, info, s);
     if (persist) return persist_run(a, mixed, t, w, info, s);
 
     // Enqueue chunks of K iterations + one refresh kernel; poll the state of

@@ -727,3 +727,117 @@ def test_persistent_driver_barrier_timeout_is_an_error(lib):
     assert info["rc"] == CFD_EHIP
     x, info = lib.solve(A, bd, tol=1e-10, precision="fp64", driver="persistent")
     assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+
+
+RESIDENT_CASES = [  # dims, rhs kind, seed (at most 4096 cells)
+    ((16, 16, 16), "uniform", 0),
+    ((16, 16, 16), "smoothed", 5),
+    ((15, 15, 15), "smoothed", 1),
+    ((24, 13, 13), "uniform", 3),
+    ((31, 11, 7), "uniform", 4),
+    ((64, 64, 1), "uniform", 6),
+    ((1, 1, 1), "uniform", 0),
+    ((2, 1, 1), "uniform", 2),
+    ((3, 5, 2), "uniform", 7),
+]
+
+
+@pytest.mark.parametrize("dims,kind,seed", RESIDENT_CASES)
+@pytest.mark.parametrize("formulation", ["pinned", "projected"])
+def test_resident_driver_parity(lib, dims, kind, seed, formulation):
+    """The resident driver (float64, one workgroup, matrix and vectors in
+    registers and LDS) against the oracle: true residual <= tol, pressure
+    error <= 1e-9, and iteration counts within 2 % + 2 of the
+    launch-per-step driver's and (pinned) the oracle's CG."""
+    tol = 1e-10
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, kind, seed)
+    A = lib.assemble(dims, 0)
+    print(f"resident {dims} {kind} {seed} {formulation}", flush=True)
+    x, info = lib.solve(A, dev(b), tol=tol, precision="fp64", formulation=formulation, driver="resident")
+    x = host(x)
+    assert info["status"] == 0
+    if not np.any(b):
+        assert not np.any(x) and info["iters"] == 0
+        return
+    assert info["rel_residual"] <= tol and info["stop_margin"] == 1.0
+    assert x[0] == 0.0
+    rr = true_relres(ref, b, x)
+    assert rr <= tol + relres_rounding(ref, b, x)
+    assert abs(rr - info["rel_residual"]) <= 0.05 * tol + relres_rounding(ref, b, x)
+    if ref.n > 1:
+        truth = oracle.pinned_solve_spectral(dims, 0, b)
+        assert mean_removed_err(x, truth) <= 1e-9
+    _, it_steps = lib.solve(A, dev(b), tol=tol, precision="fp64", formulation=formulation, driver="steps")
+    assert abs(info["iters"] - it_steps["iters"]) <= 2 + 0.02 * it_steps["iters"], (info["iters"], it_steps["iters"])
+    if formulation == "pinned":
+        _, it_ora, _, st = oracle.cg(ref, b, tol=tol)
+        assert st == oracle.OK
+        assert abs(info["iters"] - it_ora) <= 2 + 0.02 * it_ora, (info["iters"], it_ora)
+
+
+@pytest.mark.parametrize("pin", [1, 8 * 9 * 3 + 9 * 4 + 4, 9 * 8 * 7 - 1])
+def test_resident_driver_pin_positions(lib, pin):
+    """Pinned cell on a face, inside and at the far corner: the projected
+    formulation's correction rows (the pin and its neighbours) are handled
+    in the resident kernel as in the other drivers."""
+    dims = (9, 8, 7)
+    ref = oracle.assemble(dims, pin)
+    b = oracle.rhs_prepare(synth.uniform_rhs(dims, 11), pin)
+    truth = oracle.pinned_solve_spectral(dims, pin, b)
+    A = lib.assemble(dims, pin)
+    for form in ("pinned", "projected"):
+        x, info = lib.solve(A, dev(b), tol=1e-10, precision="fp64", formulation=form, driver="resident")
+        x = host(x)
+        assert info["status"] == 0 and x[pin] == 0.0
+        assert true_relres(ref, b, x) <= 1e-10 + relres_rounding(ref, b, x)
+        assert mean_removed_err(x, truth) <= 1e-9
+
+
+def test_resident_driver_options_and_errors(lib):
+    """Resident driver with x0, a warm-start network, b = 0, a stopping
+    margin, the iteration cap and a forced breakdown: the outcomes of the
+    launch-per-step driver.  Float64 grids up to 4096 cells take it by
+    default; mixed precision or a larger grid asked to take it is an error."""
+    from paper_2504_03697_amd._lib import CFD_EBREAKDOWN, CFD_EINVAL, CFD_ENOCONV
+    dims = (16, 16, 16)
+    ref = oracle.assemble(dims, 0)
+    b = make_rhs(dims, "uniform", 8)
+    A = lib.assemble(dims, 0)
+    bd = dev(b)
+    x0 = dev(synth.uniform_rhs(dims, 9))
+    xs, i_s = lib.solve(A, bd, x0=x0, tol=1e-10, precision="fp64", driver="steps")
+    xr, i_r = lib.solve(A, bd, x0=x0, tol=1e-10, precision="fp64", driver="resident")
+    assert i_r["status"] == 0 and abs(i_s["iters"] - i_r["iters"]) <= 2
+    assert i_r["init_residual"] == pytest.approx(i_s["init_residual"], rel=1e-12)
+    np.testing.assert_allclose(host(xr), host(xs), rtol=0, atol=1e-8 * np.abs(host(xs)).max())
+    net = lib.Net(synth.net_init(3))
+    for form in ("pinned", "projected"):
+        xn, i_n = lib.solve(A, bd, tol=1e-10, precision="fp64", formulation=form, net=net, driver="resident")
+        _, i_ns = lib.solve(A, bd, tol=1e-10, precision="fp64", formulation=form, net=net, driver="steps")
+        assert i_n["status"] == 0 and i_n["gamma"] == i_ns["gamma"] and i_n["used_fallback"] == i_ns["used_fallback"]
+        assert true_relres(ref, b, host(xn)) <= 1e-10 + relres_rounding(ref, b, host(xn))
+    z, iz = lib.solve(A, dev(np.zeros(ref.n)), tol=1e-10, precision="fp64", driver="resident")
+    assert iz["status"] == 0 and iz["iters"] == 0 and not np.any(host(z))
+    xm, im = lib.solve(A, bd, tol=1e-10, precision="fp64", stop_margin=0.1, driver="resident")
+    assert im["stop_margin"] == 0.1 and im["rel_residual"] <= 1e-11
+    assert true_relres(ref, b, host(xm)) <= 1e-11 + relres_rounding(ref, b, host(xm))
+    # the iteration cap and a breakdown leave the same iterate
+    xc, ic = lib.solve(A, bd, tol=1e-10, precision="fp64", max_iters=30, driver="resident", raise_on_error=False)
+    assert ic["rc"] == CFD_ENOCONV and ic["iters"] == 30
+    xcs, _ = lib.solve(A, bd, tol=1e-10, precision="fp64", max_iters=30, driver="steps", raise_on_error=False)
+    assert np.abs(host(xc) - host(xcs)).max() <= 1e-10 * np.abs(host(xcs)).max()
+    xb, ib = lib.solve(A, bd, tol=1e-10, precision="fp64", debug_breakdown_at=31, driver="resident",
+                       raise_on_error=False)
+    assert ib["rc"] == CFD_EBREAKDOWN and ib["iters"] == 31
+    assert np.array_equal(host(xb), host(xc))
+    # deterministic, and the default for float64 at this size
+    x1, i1 = lib.solve(A, bd, tol=1e-10, precision="fp64", driver="resident")
+    x2, i2 = lib.solve(A, bd, tol=1e-10, precision="fp64")
+    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
+    _, e1 = lib.solve(A, bd, tol=1e-10, precision="mixed", driver="resident", raise_on_error=False)
+    assert e1["rc"] == CFD_EINVAL
+    A17 = lib.assemble(17, 0)
+    _, e2 = lib.solve(A17, dev(make_rhs((17, 17, 17), "uniform", 1)), tol=1e-10, precision="fp64", driver="resident",
+                      raise_on_error=False)
+    assert e2["rc"] == CFD_EINVAL
