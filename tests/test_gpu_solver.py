@@ -123,6 +123,28 @@ def test_spmv_full_size_256(lib):
     np.testing.assert_array_equal(y, oracle.spmv(ref, x.astype(np.float64)))
 
 
+@pytest.mark.parametrize("dims,pin", [((256, 128, 128), 0), ((256, 17, 1000), 4 * 256 * 17 + 9 * 256 + 100),
+                                      ((256, 1, 16400), 0), ((256, 16400, 1), 77), ((256, 130, 127), 256 * 130 * 127 - 1)])
+def test_spmv_plane_marching_shapes(lib, dims, pin):
+    """Grids with 256-cell x-rows and at least 2^22 rows take the
+    plane-marching float32 SpMV: ny not a multiple of 8 and nz not a
+    multiple of its 8-plane range, ny = 1 (the z offset equals the x-row
+    length), nz = 1, and pins inside and at the last cell.  Integer vectors:
+    bit-exact against the oracle; real vectors: within 2 gamma_7 |A||x|."""
+    A = lib.assemble(dims, pin)
+    ref = oracle.assemble(dims, pin)
+    rng = np.random.default_rng(13)
+    xi = rng.integers(-8, 9, size=ref.n).astype(np.float32)
+    y = host(lib.spmv(A, dev(xi, torch.float32))).astype(np.float64)
+    np.testing.assert_array_equal(y, oracle.spmv(ref, xi.astype(np.float64)))
+    x32 = rng.uniform(-1, 1, size=ref.n).astype(np.float32)
+    absA = oracle.Csr(ref.row_ptr, ref.col, np.abs(ref.val), ref.dims, ref.pin)
+    y_ref = oracle.spmv(ref, x32.astype(np.float64))
+    bound = 2 * 7 * 2.0**-24 * oracle.spmv(absA, np.abs(x32.astype(np.float64))) * 1.01
+    y32 = host(lib.spmv(A, dev(x32, torch.float32))).astype(np.float64)
+    assert np.all(np.abs(y32 - y_ref) <= bound)
+
+
 # ---------------------------------------------------------------- symmetric storage
 
 SYM_CASES = [((1, 1, 1), 0), ((1, 1, 1), -1), ((2, 1, 1), 1), ((3, 1, 2), 0), ((5, 7, 3), 52),
