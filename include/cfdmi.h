@@ -221,15 +221,15 @@ typedef struct cfd_solve_opts {
                             cooperative launch runs every iteration, its
                             steps separated by grid barriers (CFD_EINVAL if
                             the device cannot launch cooperatively).
-                            CFD_DRIVER_RESIDENT: float64 solves of at most
-                            4096 cells (16^3): one workgroup runs the whole
-                            solve with the matrix and vectors in registers
-                            and LDS (CFD_EINVAL for mixed precision or a
-                            larger grid).
-                            CFD_DRIVER_AUTO (0): resident for float64 up to
-                            4096 cells; else persistent for grids of at
-                            most 24^3 cells, where launch overhead sets the
-                            iteration time; else one launch per step.      */
+                            CFD_DRIVER_RESIDENT: grids of at most 4096 cells
+                            (16^3), both precisions: one workgroup runs the
+                            whole solve with the matrix and vectors in
+                            registers and LDS (CFD_EINVAL for a larger
+                            grid).
+                            CFD_DRIVER_AUTO (0): resident up to 4096 cells;
+                            else persistent for grids of at most 24^3
+                            cells, where launch overhead sets the iteration
+                            time; else one launch per step.                */
     int32_t barrier_spins; /* persistent driver: polls before a grid barrier
                             wait gives up (<= 0: about 4M, ~0.3 s); the
                             solve then ends with CFD_EHIP.  Testing only.  */

@@ -913,13 +913,15 @@ enum ResOp : int32_t { OP_END = 0, OP_REFRESH = 1, OP_STEP = 2, OP_FINAL = 3 };
 struct ResCtl {
     CgState st;
     double beta, shift, alpha;
-    int32_t op, normal, zero_x, update;
+    double cref, inv_s, sa;  // mixed: restart coefficient, 1 / s, s alpha
+    int32_t op, normal, use_p, zero_x, update;
 };
 
 // Thread 0: the next operation from the control state and the latest sums.
 // Not inlined: the decision's temporaries then take call-clobbered
 // registers instead of competing with the rows each thread keeps.  The
 // arguments are the fields of SolveArgs that the decision reads.
+template <bool MIXED>
 __device__ __noinline__ void res_control(double *tolv, double ru_delta, int32_t max_iters, int32_t proj,
                                          double bpin, ResCtl *cp, double rr, double rrp, double bb) {
     SolveArgs a{};
@@ -939,7 +941,7 @@ __device__ __noinline__ void res_control(double *tolv, double ru_delta, int32_t 
             c.op = OP_REFRESH;
             return;
         }
-        const Decision D = decide_core<false>(a, c.st, rr, rrp, bb);
+        const Decision D = decide_core<MIXED>(a, c.st, rr, rrp, bb);
         if (D.stop) {
             c.st = D.ns;
             if (D.ns.done) {
@@ -952,7 +954,10 @@ __device__ __noinline__ void res_control(double *tolv, double ru_delta, int32_t 
         }
         c.op = OP_STEP;
         c.beta = D.beta;
+        c.cref = D.cref;
+        c.inv_s = D.inv_s;
         c.normal = c.st.mode == MODE_NORMAL;
+        c.use_p = c.st.mode == MODE_NORMAL || c.st.mode == MODE_REFRESH;
         c.st = D.ns;
         return;
     }
@@ -968,11 +973,18 @@ __device__ __forceinline__ void res_for(F &&f) {
     }
 }
 
+// MIXED: the launch-per-step mixed path's arithmetic (a32_body, b_body,
+// f_body): float32 r, q and direction, the direction gathered as float32,
+// x and the refreshed residual r64 in float64; x takes s alpha p at once
+// (the same fma, in the same order, as the queue applies it).
+template <bool MIXED>
 __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t t) {
+    typedef typename std::conditional<MIXED, float, double>::type VT;
     __shared__ float s_val[kResRows * kMaxRowNnz * kResThreads];  // [row slot][entry][thread]
-    __shared__ double s_v[kResMaxRows];
+    __shared__ double s_v[kResMaxRows];  // the direction (as VT), or x during a refresh
     __shared__ double red[kResThreads / 64];
     __shared__ ResCtl ctl;
+    VT *s_p = reinterpret_cast<VT *>(s_v);
     const int tid = threadIdx.x;
     const int64_t n = a.n;
     constexpr int kPacked = (kMaxRowNnz + 1) / 2;
@@ -980,7 +992,13 @@ __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t 
     // per row slot k, 4 bits at 4k: the row length (0..7), and bit 3 set for
     // the rows the projected formulation corrects (the pin and its neighbours)
     uint32_t meta = 0u;
-    double x[kResRows], r[kResRows], q[kResRows];
+    // float64: r in r64; mixed: r in units of s in r32, and the float64
+    // residual of cg_init and of each refresh in a.r (read back by the same
+    // thread in the step after it: out of the registers the loop carries)
+    double x[kResRows];
+    double r64[kResRows];
+    VT r32[kResRows], q[kResRows];
+    VT pk[kResRows];  // mixed: this thread's rows of the direction
     auto row = [&](auto kc) -> int64_t { return tid + (int64_t)decltype(kc)::value * kResThreads; };
     res_for<kResRows>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
@@ -999,24 +1017,27 @@ __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t 
             s_val[(k * kMaxRowNnz + e) * kResThreads + tid] = e < len ? a.v32[e0 + e] : 0.0f;
         }
         x[k] = own ? a.x[i] : 0.0;
-        r[k] = own ? a.r[i] : 0.0;
-        q[k] = 0.0;
+        r64[k] = (!MIXED && own) ? a.r[i] : 0.0;
+        r32[k] = q[k] = pk[k] = (VT)0;
     });
-    // row k of A (A_neu in the projected formulation) times the vector in s_v
-    auto sv = [&](int32_t j) -> double { return s_v[j]; };
-    auto rowprod = [&](auto kc) -> double {
+    // row k of A (A_neu in the projected formulation) times the vector in
+    // s_v (float64: the direction or x) or, mixed, in s_p (the direction)
+    auto sv64 = [&](int32_t j) -> double { return s_v[j]; };
+    auto svp = [&](int32_t j) -> VT { return s_p[j]; };
+    auto rowprod = [&](auto kc, auto g) {
+        using T = decltype(g(0));
         constexpr int k = decltype(kc)::value;
         const int32_t i = (int32_t)row(kc);
         const uint32_t m = (meta >> (4 * k)) & 15u;
         const int len = (int)(m & 7u);
-        double acc = 0.0;
+        T acc = T(0);
 #pragma unroll
         for (int e = 0; e < kMaxRowNnz; ++e)
             if (e < len) {
                 const int32_t j = i + (int32_t)(int16_t)(cc[k][e / 2] >> (16 * (e & 1)));
-                acc = fma((double)s_val[(k * kMaxRowNnz + e) * kResThreads + tid], s_v[j], acc);
+                acc = fma(T(s_val[(k * kMaxRowNnz + e) * kResThreads + tid]), g(j), acc);
             }
-        return (m & 8u) ? neu_fix(a, (int64_t)i, acc, sv) : acc;
+        return (m & 8u) ? neu_fix(a, (int64_t)i, acc, g) : acc;
     };
     // the first decision reduces the partial sums cg_init left
     if (tid == 0) ctl.st = a.S[t & 1];
@@ -1033,7 +1054,7 @@ __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t 
     }
     const double bpin = a.proj ? a.b[a.pin] : 0.0;
     for (;;) {
-        if (tid == 0) res_control(a.tolv, a.ru_delta, a.max_iters, a.proj, bpin, &ctl, rr, rrp, bb);
+        if (tid == 0) res_control<MIXED>(a.tolv, a.ru_delta, a.max_iters, a.proj, bpin, &ctl, rr, rrp, bb);
         __syncthreads();
         const int32_t op = ctl.op;
         if (op == OP_END) break;
@@ -1047,31 +1068,81 @@ __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t 
             });
             break;
         }
-        // Refresh: r = c - A x at the current iterate (x gathered from s_v).
-        // A step: p = r + beta p_old (after a restart p = r) into s_v; q = A p.
-        const bool refresh = op == OP_REFRESH;
+        if constexpr (MIXED) {
+            if (op == OP_REFRESH) {
+                // r64 = c - A x at the current iterate (x gathered from s_v)
+                res_for<kResRows>([&](auto kc) {
+                    const int64_t i = row(kc);
+                    if (i < n) s_v[i] = x[decltype(kc)::value];
+                });
+                __syncthreads();
+                double s1 = 0.0, s2 = 0.0;
+                res_for<kResRows>([&](auto kc) {
+                    constexpr int k = decltype(kc)::value;
+                    const int64_t i = row(kc);
+                    if (i < n) {
+                        const double ri = a.c[i] - rowprod(kc, sv64);
+                        a.r[i] = ri;
+                        s1 = fma(ri, ri, s1);
+                        if (!(a.proj && i == a.pin)) s2 = fma(ri, ri, s2);
+                    }
+                });
+                const double xpin = s_v[a.pin];
+                rr = block_sum<kResThreads>(s1, red);
+                rrp = block_sum<kResThreads>(s2, red);
+                bb = 0.0;
+                if (tid == 0) {
+                    ctl.st.pending = 0;
+                    ctl.st.mode = MODE_REFRESH;
+                    ctl.st.updates += 1;
+                    ctl.st.xpin = xpin;
+                }
+                continue;
+            }
+        }
+        // Float64: one pass serves the refresh (r = c - A x, x gathered from
+        // s_v) and the A step (p = r + beta p_old, after a restart p = r,
+        // into s_v; q = A p; p^T q).  Mixed A step: r = r64 / s after a
+        // restart; p = r + beta p_old (normal), r + cref p_old (refresh) or
+        // r (first step); q = A p; p^T q.
+        const bool refresh = !MIXED && op == OP_REFRESH;
         const bool normal = ctl.normal != 0;
         const double beta = ctl.beta;
-        res_for<kResRows>([&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            const int64_t i = row(kc);
-            if (i < n) s_v[i] = refresh ? x[k] : normal ? fma(beta, s_v[i], r[k]) : r[k];
-        });
+        if constexpr (MIXED) {
+            const bool use_p = ctl.use_p != 0;
+            const float cf = normal ? (float)beta : (float)ctl.cref;
+            const double inv_s = ctl.inv_s;
+            res_for<kResRows>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const int64_t i = row(kc);
+                if (i < n) {
+                    if (!normal) r32[k] = (float)(a.r[i] * inv_s);
+                    pk[k] = use_p ? fmaf(cf, pk[k], r32[k]) : r32[k];
+                    s_p[i] = pk[k];
+                }
+            });
+        } else {
+            res_for<kResRows>([&](auto kc) {
+                constexpr int k = decltype(kc)::value;
+                const int64_t i = row(kc);
+                if (i < n) s_v[i] = refresh ? x[k] : normal ? fma(beta, s_v[i], r64[k]) : r64[k];
+            });
+        }
         __syncthreads();
         double s1 = 0.0, s2 = 0.0;
         res_for<kResRows>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             const int64_t i = row(kc);
             if (i < n) {
-                const double prod = rowprod(kc);
+                const VT prod = rowprod(kc, svp);
                 if (refresh) {
-                    const double ri = a.c[i] - prod;
-                    r[k] = ri;
+                    const double ri = a.c[i] - (double)prod;
+                    r64[k] = ri;
                     s1 = fma(ri, ri, s1);
                     if (!(a.proj && i == a.pin)) s2 = fma(ri, ri, s2);
                 } else {
                     q[k] = prod;
-                    s1 = fma(s_v[i], prod, s1);  // p^T q
+                    s1 = fma((double)s_p[i], (double)prod, s1);  // p^T q
                 }
             }
         });
@@ -1089,7 +1160,7 @@ __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t 
             continue;
         }
         const double pq = block_sum<kResThreads>(s1, red);
-        // B step: alpha = rho / p^T q; x += alpha p; r -= alpha q; ||r||^2
+        // B step: alpha = rho / p^T q; x += (s) alpha p; r -= alpha q; ||r||^2
         if (tid == 0) {
             ctl.st.mode = MODE_NORMAL;
             ctl.st.iters += 1;
@@ -1102,19 +1173,26 @@ __global__ void __launch_bounds__(kResThreads) cg_resident(SolveArgs a, int64_t 
             } else {
                 ctl.update = 1;
                 ctl.alpha = alpha;
+                ctl.sa = ctl.st.scale * alpha;
             }
         }
         __syncthreads();
         if (ctl.update) {
-            const double alpha = ctl.alpha;
+            const double alpha = ctl.alpha, sa = ctl.sa;
             double s1 = 0.0;
             res_for<kResRows>([&](auto kc) {
                 constexpr int k = decltype(kc)::value;
                 const int64_t i = row(kc);
                 if (i < n) {
-                    x[k] = fma(alpha, s_v[i], x[k]);  // s_v still holds p
-                    r[k] = fma(-alpha, q[k], r[k]);
-                    s1 = fma(r[k], r[k], s1);
+                    if constexpr (MIXED) {
+                        x[k] = fma(sa, (double)pk[k], x[k]);
+                        r32[k] = fmaf(-(float)alpha, q[k], r32[k]);
+                        s1 = fma((double)r32[k], (double)r32[k], s1);
+                    } else {
+                        x[k] = fma(alpha, s_v[i], x[k]);  // s_v still holds p
+                        r64[k] = fma(-alpha, q[k], r64[k]);
+                        s1 = fma(r64[k], r64[k], s1);
+                    }
                 }
             });
             rr = block_sum<kResThreads>(s1, red);
@@ -1259,8 +1337,9 @@ static int rb_solve_impl(cfd_csr_t A, const double *b, const double *x0, double 
 // Run the resident driver after cg_init and fill info the same way.
 static int finish_single_launch(int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s);
 
-static int resident_run(SolveArgs &a, int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s) {
-    hipLaunchKernelGGL(cg_resident, dim3(1), dim3(kResThreads), 0, s, a, t);
+static int resident_run(SolveArgs &a, bool mixed, int64_t t, Workspace *w, cfd_solve_info *info, hipStream_t s) {
+    if (mixed) hipLaunchKernelGGL(cg_resident<true>, dim3(1), dim3(kResThreads), 0, s, a, t);
+    else hipLaunchKernelGGL(cg_resident<false>, dim3(1), dim3(kResThreads), 0, s, a, t);
     CFD_HIP(hipGetLastError());
     return finish_single_launch(t, w, info, s);
 }
@@ -1386,11 +1465,11 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     if (opts.driver != CFD_DRIVER_AUTO && opts.driver != CFD_DRIVER_STEPS && opts.driver != CFD_DRIVER_PERSISTENT &&
         opts.driver != CFD_DRIVER_RESIDENT)
         return fail(CFD_EINVAL, "cfd_solve: unknown driver");
-    if (opts.driver == CFD_DRIVER_RESIDENT && (mixed || A->n > kResMaxRows))
-        return fail(CFD_EINVAL, "cfd_solve: the resident driver takes float64 solves of at most " +
+    if (opts.driver == CFD_DRIVER_RESIDENT && A->n > kResMaxRows)
+        return fail(CFD_EINVAL, "cfd_solve: the resident driver takes grids of at most " +
                                     std::to_string(kResMaxRows) + " cells");
     const bool resident = opts.driver == CFD_DRIVER_RESIDENT ||
-                          (opts.driver == CFD_DRIVER_AUTO && !mixed && A->n <= kResMaxRows);
+                          (opts.driver == CFD_DRIVER_AUTO && A->n <= kResMaxRows);
     bool persist = !resident && (opts.driver == CFD_DRIVER_PERSISTENT ||
                                  (opts.driver == CFD_DRIVER_AUTO && A->n <= kPersistMaxRows));
     if (persist) {
@@ -1424,7 +1503,7 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     else hipLaunchKernelGGL(cg_init<false>, dim3(a.Gf), dim3(kBlock), 0, s, a, t);
     ++t;
     CFD_HIP(hipGetLastError());
-    if (resident) return resident_run(a, t, w, info, s);
+    if (resident) return resident_run(a, mixed, t, w, info, s);
     if (persist) return persist_run(a, mixed, t, w, info, s);
 
     // Enqueue chunks of K iterations + one refresh kernel; poll the state of

@@ -766,33 +766,38 @@ RESIDENT_CASES = [  # dims, rhs kind, seed (at most 4096 cells)
 
 @pytest.mark.parametrize("dims,kind,seed", RESIDENT_CASES)
 @pytest.mark.parametrize("formulation", ["pinned", "projected"])
-def test_resident_driver_parity(lib, dims, kind, seed, formulation):
-    """The resident driver (float64, one workgroup, matrix and vectors in
-    registers and LDS) against the oracle: true residual <= tol, pressure
-    error <= 1e-9, and iteration counts within 2 % + 2 of the
-    launch-per-step driver's and (pinned) the oracle's CG."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_resident_driver_parity(lib, dims, kind, seed, formulation, precision):
+    """The resident driver (one workgroup, matrix and vectors in registers
+    and LDS) against the oracle: true residual <= tol times the stopping
+    margin, pressure error <= 1e-9, and iteration counts within 2 % + 2
+    (float64; mixed: 10 % + 5, float32 rounding of other groupings) of the
+    launch-per-step driver's and, float64 pinned, the oracle's CG."""
     tol = 1e-10
     ref = oracle.assemble(dims, 0)
     b = make_rhs(dims, kind, seed)
     A = lib.assemble(dims, 0)
-    print(f"resident {dims} {kind} {seed} {formulation}", flush=True)
-    x, info = lib.solve(A, dev(b), tol=tol, precision="fp64", formulation=formulation, driver="resident")
+    print(f"resident {dims} {kind} {seed} {formulation} {precision}", flush=True)
+    x, info = lib.solve(A, dev(b), tol=tol, precision=precision, formulation=formulation, driver="resident")
     x = host(x)
     assert info["status"] == 0
     if not np.any(b):
         assert not np.any(x) and info["iters"] == 0
         return
-    assert info["rel_residual"] <= tol and info["stop_margin"] == 1.0
+    _, it_steps = lib.solve(A, dev(b), tol=tol, precision=precision, formulation=formulation, driver="steps")
+    assert info["stop_margin"] == it_steps["stop_margin"]
+    stop = tol * info["stop_margin"]
+    assert info["rel_residual"] <= stop
     assert x[0] == 0.0
     rr = true_relres(ref, b, x)
-    assert rr <= tol + relres_rounding(ref, b, x)
-    assert abs(rr - info["rel_residual"]) <= 0.05 * tol + relres_rounding(ref, b, x)
+    assert rr <= stop + relres_rounding(ref, b, x)
+    assert abs(rr - info["rel_residual"]) <= 0.05 * stop + relres_rounding(ref, b, x)
     if ref.n > 1:
         truth = oracle.pinned_solve_spectral(dims, 0, b)
         assert mean_removed_err(x, truth) <= 1e-9
-    _, it_steps = lib.solve(A, dev(b), tol=tol, precision="fp64", formulation=formulation, driver="steps")
-    assert abs(info["iters"] - it_steps["iters"]) <= 2 + 0.02 * it_steps["iters"], (info["iters"], it_steps["iters"])
-    if formulation == "pinned":
+    slack = 2 + 0.02 * it_steps["iters"] if precision == "fp64" else 5 + 0.1 * it_steps["iters"]
+    assert abs(info["iters"] - it_steps["iters"]) <= slack, (info["iters"], it_steps["iters"])
+    if precision == "fp64" and formulation == "pinned":
         _, it_ora, _, st = oracle.cg(ref, b, tol=tol)
         assert st == oracle.OK
         assert abs(info["iters"] - it_ora) <= 2 + 0.02 * it_ora, (info["iters"], it_ora)
@@ -819,8 +824,8 @@ def test_resident_driver_pin_positions(lib, pin):
 def test_resident_driver_options_and_errors(lib):
     """Resident driver with x0, a warm-start network, b = 0, a stopping
     margin, the iteration cap and a forced breakdown: the outcomes of the
-    launch-per-step driver.  Float64 grids up to 4096 cells take it by
-    default; mixed precision or a larger grid asked to take it is an error."""
+    launch-per-step driver, in both precisions.  Grids up to 4096 cells take
+    it by default; a larger grid asked to take it is an error."""
     from paper_2504_03697_amd._lib import CFD_EBREAKDOWN, CFD_EINVAL, CFD_ENOCONV
     dims = (16, 16, 16)
     ref = oracle.assemble(dims, 0)
@@ -853,12 +858,27 @@ def test_resident_driver_options_and_errors(lib):
                        raise_on_error=False)
     assert ib["rc"] == CFD_EBREAKDOWN and ib["iters"] == 31
     assert np.array_equal(host(xb), host(xc))
-    # deterministic, and the default for float64 at this size
-    x1, i1 = lib.solve(A, bd, tol=1e-10, precision="fp64", driver="resident")
-    x2, i2 = lib.solve(A, bd, tol=1e-10, precision="fp64")
-    assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
-    _, e1 = lib.solve(A, bd, tol=1e-10, precision="mixed", driver="resident", raise_on_error=False)
-    assert e1["rc"] == CFD_EINVAL
+    # deterministic, and the default at this size
+    for prec in ("fp64", "mixed"):
+        x1, i1 = lib.solve(A, bd, tol=1e-10, precision=prec, driver="resident")
+        x2, i2 = lib.solve(A, bd, tol=1e-10, precision=prec)
+        assert i1["iters"] == i2["iters"] and torch.equal(x1, x2)
+    # mixed: warm start, b = 0, the cap and a breakdown at each position of
+    # the update queue the other drivers keep
+    for form in ("pinned", "projected"):
+        xn, i_n = lib.solve(A, bd, tol=1e-10, precision="mixed", formulation=form, net=net, driver="resident")
+        assert i_n["status"] == 0 and i_n["stop_margin"] == 0.05 and i_n["updates"] >= 1
+        assert true_relres(ref, b, host(xn)) <= 0.05e-10 + relres_rounding(ref, b, host(xn))
+    z, iz = lib.solve(A, dev(np.zeros(ref.n)), tol=1e-10, precision="mixed", driver="resident")
+    assert iz["status"] == 0 and iz["iters"] == 0 and not np.any(host(z))
+    for k in (37, 38, 39, 40):
+        xc, ic = lib.solve(A, bd, tol=1e-10, precision="mixed", max_iters=k - 1, driver="resident",
+                           raise_on_error=False)
+        assert ic["rc"] == CFD_ENOCONV and ic["iters"] == k - 1
+        xb, ib = lib.solve(A, bd, tol=1e-10, precision="mixed", debug_breakdown_at=k, driver="resident",
+                           raise_on_error=False)
+        assert ib["rc"] == CFD_EBREAKDOWN and ib["iters"] == k
+        assert np.array_equal(host(xb), host(xc))
     A17 = lib.assemble(17, 0)
     _, e2 = lib.solve(A17, dev(make_rhs((17, 17, 17), "uniform", 1)), tol=1e-10, precision="fp64", driver="resident",
                       raise_on_error=False)
