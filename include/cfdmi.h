@@ -294,7 +294,9 @@ typedef struct cfd_state {
  * Walls are no-slip; tangential values outside the domain are ghosts
  * 2*U_wall - inside (U_wall = lid_u for u on the lid, else 0).
  * Errors: CFD_EINVAL if dt <= 0 or dt*nu*6/h^2 > 1 (explicit viscosity
- * unstable), plus every cfd_solve error.  Synchronises the stream.
+ * unstable), plus every cfd_solve error; after a solve error u, v, w hold
+ * the velocities before the pressure correction, p the solver's last
+ * iterate, and t and step are not advanced.  Synchronises the stream.
  */
 int cfd_step(cfd_state *state, double dt, double tol, const cfd_solve_opts *opts,
              cfd_solve_info *info, void *stream);
