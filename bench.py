@@ -123,10 +123,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dic", action="store_true", help="skip the DIC-preconditioned comparison solves")
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2504_03697_amd", "weights", "warmstart.npy"))
+    ap.add_argument("--workload", choices=("solve", "step"), default="solve",
+                    help="solve: the headline Poisson solves; step: cavity time steps (for the step kernels)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the solver runs on a single GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "step":
+        return step_workload(args)
 
     import numpy as np
     import torch
@@ -367,6 +371,43 @@ dt1 = time.perf_counter() - t
 print(json.dumps({"seconds": dt, "iters": it, "relres": rr, "status": st, "threads": threads,
                   "setup_seconds": setup, "one_thread_iters": it1, "one_thread_seconds": dt1}))
 """
+
+
+def step_workload(args):
+    """Time steps of the cavity (Sec. 3.1 fractional step) at n^3 from a
+    random flow (synth.random_flow, |u| <= 1, seed 7), nu = 1e-3, lid 1,
+    dt = 0.4 h; each pressure solve mixed + projected to tol.  One JSON line
+    (ms per step and the solves' iterations); the step kernels' own times
+    come from a kernel trace of this run."""
+    import torch
+
+    import paper_2504_03697_amd as m
+    import synth
+
+    torch.cuda.set_device(0)
+    n = args.n
+    h = 1.0 / n
+    dt = 0.4 * h
+    S = m.State(n, nu=1e-3, lid_u=1.0)
+    for t, a in zip((S.u, S.v, S.w), synth.random_flow(n, 7)):
+        t.copy_(torch.from_numpy(a))
+    # 256 MiB device copy: the calibration kernel of the PMC byte counters
+    cal = torch.empty(32 << 20, dtype=torch.float64, device="cuda")
+    cal.copy_(torch.zeros_like(cal))
+    kw = dict(tol=args.tol, precision="mixed", formulation="projected")
+    for _ in range(args.warmup):
+        m.step(S, dt, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = [m.step(S, dt, **kw)["iters"] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    faces = 3 * n * n * (n + 1)
+    print(json.dumps({"metric": f"cavity time step, {n}^3", "value": round(ms, 3), "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "dtype": "f64",
+                      "data": "synthetic", "config": {"workload": f"cavity step {n}^3 from a random flow, nu 1e-3, "
+                                                                  f"dt 0.4 h, mixed + projected solve to {args.tol:g}",
+                                                      "faces": faces, "iters": iters}}))
 
 
 def host_cpu_info():

@@ -169,13 +169,14 @@ constexpr int kAdHX = kAdTX + 2, kAdHY = kAdTY + 2;
 constexpr int kAdHalo = kAdHX * kAdHY;  // 2046 entries: 4 passes of 512 threads
 constexpr int kAdKZ = 16;
 constexpr int kAdPasses = (kAdHalo + kAdThreads - 1) / kAdThreads;  // entries per thread and plane
-constexpr int kAdBatch = 2;  // entries whose loads are issued together
+constexpr int kAdPlane = kAdPasses * kAdThreads;                     // LDS slots per plane (2048)
+constexpr int kAdBatch = 1;  // entries whose loads are issued together
 static_assert(kAdPasses % kAdBatch == 0, "whole batches");
 
 struct AdvTiles {
     int nxt[3], nyt[3];  // tiles across x and y, per component
     int start[4];        // first tile of each component; start[3] = all tiles
-    int per_xcd;         // tiles per XCD: the grid is 8 * per_xcd workgroups
+    int per_xcd;         // slots per XCD: the grid is 8 * per_xcd workgroups
 };
 
 // Velocity component D (!= C) at an interior face (i, j, k) of C: D's faces
@@ -244,10 +245,10 @@ __device__ inline AdvPoint adv_point(const StepGrid &g, double dth, const Fields
 // One tile of component C.  Interior faces of C lie in [lo, n) in each
 // direction (lo = 1 along C, else 0; n = cells along it); the halo planes
 // hold indices x0 - 1 .. x0 + kAdTX and y0 - 1 .. y0 + kAdTY, of which those
-// above n are never read and stay unset.
+// above n are never read.
 template <int C>
 __device__ void advdiff_tile(const StepGrid &g, double dth, double coef, const Fields &in, double *__restrict__ out,
-                             int t, const AdvTiles &T, double (*ring)[kAdHalo]) {
+                             int t, const AdvTiles &T, double (*ring)[kAdPlane]) {
     int dx, dy, dz;
     fdims(g, C, dx, dy, dz);
     const int nxt = T.nxt[C], nyt = T.nyt[C];
@@ -269,12 +270,14 @@ __device__ void advdiff_tile(const StepGrid &g, double dth, double coef, const F
                 const int e = tid + (q0 + q) * kAdThreads;
                 P[q] = adv_point<C>(g, dth, in, x0 - 1 + e % kAdHX, y0 - 1 + e / kAdHX, kk);
             }
+            // no branch between the samples (one would end the batch): every
+            // slot of the padded plane is written, those past the tile's
+            // halo or the grid are never read
+            double a[kAdBatch];
 #pragma unroll
-            for (int q = 0; q < kAdBatch; ++q) {
-                const int e = tid + (q0 + q) * kAdThreads;
-                const double a = P[q].add + P[q].mul * sample<C>(g, fc, P[q].px, P[q].py, P[q].pz);
-                if (e < kAdHalo && x0 - 1 + e % kAdHX <= g.nx && y0 - 1 + e / kAdHX <= g.ny) cur[e] = a;
-            }
+            for (int q = 0; q < kAdBatch; ++q) a[q] = P[q].add + P[q].mul * sample<C>(g, fc, P[q].px, P[q].py, P[q].pz);
+#pragma unroll
+            for (int q = 0; q < kAdBatch; ++q) cur[tid + (q0 + q) * kAdThreads] = a[q];
         }
         __syncthreads();
         const int ko = kk - 1;  // its planes ko - 1, ko, ko + 1 are in the ring now
@@ -302,16 +305,20 @@ __device__ void advdiff_tile(const StepGrid &g, double dth, double coef, const F
 // 6 waves per SIMD (3 workgroups per CU, as the LDS ring allows): 80 VGPRs
 __global__ void __launch_bounds__(kAdThreads, 6) advdiff_kernel(StepGrid g, double dth, double coef, Fields in,
                                                              Fields out, AdvTiles T) {
-    __shared__ double ring[3][kAdHalo];
+    __shared__ double ring[3][kAdPlane];
     // XCD b % 8 takes tiles [(b % 8) * per_xcd, (b % 8 + 1) * per_xcd)
+    // slot t holds tile t / 3 of component t % 3: the three components of
+    // one region run side by side and share the velocity they read in L2
+    // (component by component, each field was fetched three times)
     const int t = (int)(blockIdx.x & 7) * T.per_xcd + (int)(blockIdx.x >> 3);
-    if (t >= T.start[3]) return;
-    if (t < T.start[1])
-        advdiff_tile<0>(g, dth, coef, in, out.u, t - T.start[0], T, ring);
-    else if (t < T.start[2])
-        advdiff_tile<1>(g, dth, coef, in, out.v, t - T.start[1], T, ring);
+    const int c = t % 3, s = t / 3;
+    if (s >= T.start[c + 1] - T.start[c]) return;
+    if (c == 0)
+        advdiff_tile<0>(g, dth, coef, in, out.u, s, T, ring);
+    else if (c == 1)
+        advdiff_tile<1>(g, dth, coef, in, out.v, s, T, ring);
     else
-        advdiff_tile<2>(g, dth, coef, in, out.w, t - T.start[2], T, ring);
+        advdiff_tile<2>(g, dth, coef, in, out.w, s, T, ring);
 }
 
 static AdvTiles adv_tiles(const cfd_grid &gr) {
@@ -325,7 +332,8 @@ static AdvTiles adv_tiles(const cfd_grid &gr) {
         const int nzt = (ez + kAdKZ - 1) / kAdKZ;
         T.start[c + 1] = T.start[c] + T.nxt[c] * T.nyt[c] * nzt;
     }
-    T.per_xcd = (T.start[3] + 7) / 8;
+    const int most = std::max(std::max(T.start[1] - T.start[0], T.start[2] - T.start[1]), T.start[3] - T.start[2]);
+    T.per_xcd = (3 * most + 7) / 8;
     return T;
 }
 

@@ -18,6 +18,10 @@ Recipes (the paper uses no dataset; these stand in for its workloads):
   block per layer in tap-major order ``[tap][c_in][c_out]``.
 * ``bf16_values``: random values that are exactly representable in
   bfloat16, for kernel-level parity checks.
+* ``random_flow``: face velocities on the staggered grid, i.i.d.
+  uniform[-amp, amp] from ``default_rng(seed)`` in the order u, v, w, with
+  the wall-normal faces set to zero (a flow that exercises every departure
+  direction of the advection).
 
 Arrays are indexed ``idx = i + nx * (j + ny * k)`` (x fastest).
 """
@@ -34,6 +38,7 @@ __all__ = [
     "net_layer_shapes",
     "bf16_values",
     "bf16_round_np",
+    "random_flow",
 ]
 
 
@@ -140,3 +145,18 @@ def bf16_values(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     a = (rng.standard_normal(shape) * scale).astype(np.float32)
     return bf16_round_np(a)
+
+
+def random_flow(dims, seed: int, amp: float = 1.0):
+    """(u, v, w) flat face arrays (x fastest over each component's own face
+    grid: (nx+1) x ny x nz, nx x (ny+1) x nz, nx x ny x (nz+1)), uniform in
+    [-amp, amp], zero on the wall-normal faces."""
+    nx, ny, nz = (dims, dims, dims) if isinstance(dims, int) else dims
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-amp, amp, (nz, ny, nx + 1))
+    v = rng.uniform(-amp, amp, (nz, ny + 1, nx))
+    w = rng.uniform(-amp, amp, (nz + 1, ny, nx))
+    u[:, :, 0] = u[:, :, nx] = 0.0
+    v[:, 0, :] = v[:, ny, :] = 0.0
+    w[0] = w[nz] = 0.0
+    return u.reshape(-1), v.reshape(-1), w.reshape(-1)

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -44,19 +45,6 @@ def mr(p):
     return p - p.mean()
 
 
-def random_flow(dims, seed):
-    """Random face velocities in [-1, 1] with zero wall-normal faces."""
-    nx, ny, nz = dims
-    rng = np.random.default_rng(seed)
-    u = rng.uniform(-1, 1, (nz, ny, nx + 1))
-    v = rng.uniform(-1, 1, (nz, ny + 1, nx))
-    w = rng.uniform(-1, 1, (nz + 1, ny, nx))
-    u[:, :, 0] = u[:, :, nx] = 0.0
-    v[:, 0, :] = v[:, ny, :] = 0.0
-    w[0] = w[nz] = 0.0
-    return u.reshape(-1), v.reshape(-1), w.reshape(-1)
-
-
 # shapes over several advection tiles (64 x 29 faces, 16 planes per chunk)
 # with ragged tails, one exactly one tile plus a face, and a single-cell width
 TILED_SHAPES = [((70, 33, 20), 0.01, 3), ((65, 30, 17), 0.0, 4), ((130, 8, 3), 0.02, 5), ((1, 5, 4), 0.01, 6),
@@ -78,7 +66,7 @@ def test_advection_viscosity_against_oracle_primitives(lib, dims, nu, seed):
     in rounding only: the face velocity as an exact 4-face mean)."""
     from paper_2504_03697_amd._lib import CFD_ENOCONV
     h, dt = tiled_dt(dims, nu)
-    u0, v0, w0 = random_flow(dims, seed)
+    u0, v0, w0 = synth.random_flow(dims, seed)
     S = lib.State(dims, nu=nu, lid_u=0.7)
     for t, a in ((S.u, u0), (S.v, v0), (S.w, w0)):
         t.copy_(torch.from_numpy(a))
@@ -99,7 +87,7 @@ def test_step_multi_tile_shapes_random_flow(lib, dims, nu, seed):
     """Two full steps from a random flow on the tiled shapes against the
     oracle's steps, to the float64 step bar."""
     h, dt = tiled_dt(dims, nu)
-    u0, v0, w0 = random_flow(dims, seed)
+    u0, v0, w0 = synth.random_flow(dims, seed)
     S = lib.State(dims, nu=nu, lid_u=0.7)
     R = oracle.State(dims, nu=nu, lid=0.7)
     for t, a in ((S.u, u0), (S.v, v0), (S.w, w0)):
