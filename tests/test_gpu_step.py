@@ -82,6 +82,31 @@ def test_advection_viscosity_against_oracle_primitives(lib, dims, nu, seed):
         assert np.abs(host(got) - want).max() <= 1e-12 * sc
 
 
+def test_advection_viscosity_256_full_size(lib):
+    """The fused advection + viscosity kernel at 256^3, the size and launch
+    of the step workload (4 x 9 x 16 tiles per component), on its random
+    flow (|u| <= 1, dt = 0.4 h) against the oracle's advect then diffuse on
+    every face: max error <= 1e-12 of the field's scale."""
+    from paper_2504_03697_amd._lib import CFD_ENOCONV
+    n, nu = 256, 1e-3
+    h = 1.0 / n
+    dt = 0.4 * h
+    u0, v0, w0 = synth.random_flow(n, 7)
+    S = lib.State(n, nu=nu, lid_u=1.0)
+    for t, a in ((S.u, u0), (S.v, v0), (S.w, w0)):
+        t.copy_(torch.from_numpy(a))
+    print("advection 256^3", flush=True)
+    with pytest.raises(lib.CfdError) as e:
+        lib.step(S, dt, tol=1e-10, max_iters=1)
+    assert e.value.code == CFD_ENOCONV
+    got = [host(S.u), host(S.v), host(S.w)]
+    del S
+    want = oracle.diffuse(n, h, 1.0, dt, nu, *oracle.advect(n, h, 1.0, dt, u0, v0, w0))
+    sc = max(np.abs(a).max() for a in want)
+    for g, w_ in zip(got, want):
+        assert np.abs(g - w_).max() <= 1e-12 * sc
+
+
 @pytest.mark.parametrize("dims,nu,seed", TILED_SHAPES)
 def test_step_multi_tile_shapes_random_flow(lib, dims, nu, seed):
     """Two full steps from a random flow on the tiled shapes against the
