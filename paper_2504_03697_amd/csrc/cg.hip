@@ -241,6 +241,16 @@ double *warm_buffer(cfd_csr_t A) {
 
 __device__ inline bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
+// The control state, staged once per workgroup in LDS as st.  Read by value
+// in every lane, its 160 bytes (and the next state built from it) went
+// through per-lane scratch: at 64^3 that was three times the vector traffic
+// of the float64 B kernel.
+#define CG_STATE(t)                                \
+    __shared__ CgState s_st;                       \
+    if (threadIdx.x == 0) s_st = a.S[(t) & 1];     \
+    __syncthreads();                               \
+    const CgState &st = s_st
+
 // Projected formulation.  The stored matrix is the pinned one, A_pin; the
 // Neumann matrix differs from it only in the pinned row (which becomes
 // deg*e_pin - sum of its neighbours) and in the pinned column (-1 in each
@@ -631,23 +641,15 @@ __global__ void __launch_bounds__(B, 8) cg_a32(SolveArgs a, int64_t t) {
 }
 
 // B step: alpha = rho / p^T q; r -= alpha q; partial sums of r^T r.
+// Returns false (and touches nothing) when the step length is rejected.
 template <bool MIXED>
-__device__ __forceinline__ CgState b_body(const SolveArgs &a, const CgState &st, double *red) {
+__device__ __forceinline__ bool b_core(const SolveArgs &a, const CgState &st, double *red, double &alpha,
+                                       double &sa_new) {
     const double pq = reduce_partials(a.partA, a.Ga, red);
-    const double alpha = st.rho / pq;
-    if (!(pq > 0.0) || !std::isfinite(alpha) || st.iters == a.break_at) {
-        CgState ns = st;
-        ns.pending = 1;
-        ns.reason = R_BREAKDOWN;
-        ns.alpha = 0.0;
-        // mixed: this iteration's direction is not queued, so the newest
-        // queued update is the one before it; point pcur back at it
-        // (pend_slot() counts the queue back from pcur)
-        if (MIXED) ns.pcur = (st.pcur - 1 + kRing) % kRing;
-        return ns;
-    }
+    alpha = st.rho / pq;
+    if (!(pq > 0.0) || !std::isfinite(alpha) || st.iters == a.break_at) return false;
     double rr = 0.0;
-    double sa_new = 0.0;
+    sa_new = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t first = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if constexpr (MIXED) {
@@ -731,7 +733,23 @@ __device__ __forceinline__ CgState b_body(const SolveArgs &a, const CgState &st,
     }
     rr = block_sum(rr, red);
     if (threadIdx.x == 0) a.partB[blockIdx.x] = rr;
+    return true;
+}
+
+// The state after a B step (ok: its step length was accepted).
+template <bool MIXED>
+__device__ __forceinline__ CgState b_next(const CgState &st, bool ok, double alpha, double sa_new) {
     CgState ns = st;
+    if (!ok) {
+        ns.pending = 1;
+        ns.reason = R_BREAKDOWN;
+        ns.alpha = 0.0;
+        // mixed: this iteration's direction is not queued, so the newest
+        // queued update is the one before it; point pcur back at it
+        // (pend_slot() counts the queue back from pcur)
+        if (MIXED) ns.pcur = (st.pcur - 1 + kRing) % kRing;
+        return ns;
+    }
     ns.alpha = alpha;
     if (MIXED) {
         if (st.npend < kDefer - 1) {
@@ -740,7 +758,7 @@ __device__ __forceinline__ CgState b_body(const SolveArgs &a, const CgState &st,
                 if (e == st.npend) ns.sa[e] = sa_new;
             ns.npend = st.npend + 1;
         } else {
-            ns.npend = 0;  // applied above
+            ns.npend = 0;  // applied in b_core
         }
     }
     return ns;
@@ -749,14 +767,15 @@ __device__ __forceinline__ CgState b_body(const SolveArgs &a, const CgState &st,
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_b(SolveArgs a, int64_t t) {
     __shared__ double red[kBlock / 64];
-    const CgState st = a.S[t & 1];
+    CG_STATE(t);
     CgState *out = &a.S[(t + 1) & 1];
     if (st.done || st.pending) {
         if (lead()) *out = st;
         return;
     }
-    const CgState ns = b_body<MIXED>(a, st, red);
-    if (lead()) *out = ns;
+    double alpha, sa_new;
+    const bool ok = b_core<MIXED>(a, st, red, alpha, sa_new);
+    if (lead()) *out = b_next<MIXED>(st, ok, alpha, sa_new);
 }
 
 // F kernel: when a refresh is pending, r = c - A x' in float64 with the
@@ -797,7 +816,7 @@ __device__ __forceinline__ CgState f_body(const SolveArgs &a, const CgState &st,
 template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) cg_refresh(SolveArgs a, int64_t t) {
     CG_SHARED(float);
-    const CgState st = a.S[t & 1];
+    CG_STATE(t);
     CgState *out = &a.S[(t + 1) & 1];
     if (st.done || !st.pending) {
         if (lead()) *out = st;
@@ -882,7 +901,9 @@ __global__ void __launch_bounds__(kBlock) cg_persist(SolveArgs a, int64_t t) {
         }
         st = MIXED ? a32_body(a, st, D, red, s_col, s_val) : a64_body(a, st, D, red, s_col, s_val);
         if (!(ok = grid_sync(a, seen))) break;
-        st = b_body<MIXED>(a, st, red);
+        double alpha, sa_new;
+        const bool stepped = b_core<MIXED>(a, st, red, alpha, sa_new);
+        st = b_next<MIXED>(st, stepped, alpha, sa_new);
         if (!(ok = grid_sync(a, seen))) break;
     }
     if (!ok) {
@@ -973,7 +994,7 @@ __device__ __forceinline__ void res_for(F &&f) {
     }
 }
 
-// MIXED: the launch-per-step mixed path's arithmetic (a32_body, b_body,
+// MIXED: the launch-per-step mixed path's arithmetic (a32_body, b_core,
 // f_body): float32 r, q and direction, the direction gathered as float32,
 // x and the refreshed residual r64 in float64; x takes s alpha p at once
 // (the same fma, in the same order, as the queue applies it).
@@ -1657,6 +1678,13 @@ struct RbState {
     CgState cg;
 };
 
+// The red-black solver's state staged in LDS, as CG_STATE does.
+#define RB_STATE(t)                                \
+    __shared__ RbState s_st;                       \
+    if (threadIdx.x == 0) s_st = a.S[(t) & 1];     \
+    __syncthreads();                               \
+    const RbState &st = s_st
+
 void rb_free(RbMatrix *m) {
     if (!m) return;
     void *pp[] = {m->perm, m->iperm, m->rp, m->col, m->v32, m->d64, m->d32, m->bp, m->bS, m->xb,
@@ -2210,7 +2238,7 @@ __global__ void __launch_bounds__(kBlock) rb_k2(RbArgs a, int64_t t) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) float s_val[kSlabLds];  // exact values (small integers)
     __shared__ double red[kBlock / 64];
-    const RbState st = a.S[t & 1];
+    RB_STATE(t);
     RbState *out = &a.S[(t + 1) & 1];
     if (st.cg.done || st.cg.pending) {
         if (lead()) *out = st;
@@ -2247,7 +2275,7 @@ template <bool MIXED>
 __global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
     typedef typename std::conditional<MIXED, float, double>::type VT;
     __shared__ double red[kBlock / 64];
-    const RbState st = a.S[t & 1];
+    RB_STATE(t);
     RbState *out = &a.S[(t + 1) & 1];
     if (st.cg.done || st.cg.pending) {
         if (lead()) *out = st;
@@ -2363,7 +2391,7 @@ __global__ void __launch_bounds__(kBlock) rb_b(RbArgs a, int64_t t) {
 // queued x updates (oldest first) and empty the queue, so the refresh and the
 // final x read x_b itself.
 __global__ void __launch_bounds__(kBlock) rb_apply(RbArgs a, int64_t t) {
-    const RbState st = a.S[t & 1];
+    RB_STATE(t);
     RbState *out = &a.S[(t + 1) & 1];
     if (st.cg.done || !st.cg.pending || st.cg.npend == 0) {
         if (lead()) *out = st;
@@ -2388,7 +2416,7 @@ __global__ void __launch_bounds__(kBlock) rb_apply(RbArgs a, int64_t t) {
 __global__ void __launch_bounds__(kBlock) rb_f1(RbArgs a, int64_t t) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) float s_val[kSlabLds];
-    const RbState st = a.S[t & 1];
+    RB_STATE(t);
     RbState *out = &a.S[(t + 1) & 1];
     if (lead()) *out = st;
     if (st.cg.done || !st.cg.pending) return;
@@ -2405,7 +2433,7 @@ __global__ void __launch_bounds__(kBlock) rb_f2(RbArgs a, int64_t t) {
     __shared__ __align__(16) int32_t s_col[kSlabLds];
     __shared__ __align__(16) float s_val[kSlabLds];
     __shared__ double red[kBlock / 64];
-    const RbState st = a.S[t & 1];
+    RB_STATE(t);
     RbState *out = &a.S[(t + 1) & 1];
     if (st.cg.done || !st.cg.pending) {
         if (lead()) *out = st;
