@@ -228,8 +228,9 @@ typedef struct cfd_solve_opts {
                             grid).
                             CFD_DRIVER_AUTO (0): resident up to 4096 cells;
                             else persistent for grids of at most 24^3
-                            cells, where launch overhead sets the iteration
-                            time; else one launch per step.                */
+                            cells (mixed) or 19^3 cells (float64), where
+                            launch overhead sets the iteration time; else
+                            one launch per step.                           */
     int32_t barrier_spins; /* persistent driver: polls before a grid barrier
                             wait gives up (<= 0: about 4M, ~0.3 s); the
                             solve then ends with CFD_EHIP.  Testing only.  */

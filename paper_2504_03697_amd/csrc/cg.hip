@@ -52,14 +52,17 @@ constexpr int kRing = kDefer;
 // Persistent driver.  Each grid barrier costs a few microseconds (every
 // workgroup writes back and invalidates its XCD's L2 so that the others see
 // its writes), which only beats two kernel launches per iteration on the
-// smallest grids: measured per iteration at 16^3 13.3 us against 16.6 (FP64)
-// and 22.2 (mixed) with one launch per step, at 24^3 18.1-18.7 against
-// 18.7-21.4, at 32^3 21.9-23.6 against 18.7-20.7.  So grids up to 24^3 cells
-// use it by default (CFD_DRIVER_AUTO).  At most 32 workgroups take part
+// smallest grids: measured per iteration (white noise, projected) at 17^3
+// 15.6 us against 16.2 (FP64) and 15.9 against 19.8 (mixed) with one launch
+// per step, at 20^3 15.8 against 13.6 (FP64) and 15.2 against 16.7 (mixed),
+// at 24^3 19.1 against 19.7 (mixed), at 28^3 21.2 against 18.6 (mixed).  So
+// mixed grids up to 24^3 cells and float64 grids up to 19^3 use it by
+// default (CFD_DRIVER_AUTO).  At most 32 workgroups take part
 // (fewer barrier arrivals; measured best from 24^3 to 64^3).  A barrier wait
 // gives up after kBarrierSpins polls (about 0.3 s; a step of such a grid
 // takes microseconds).
-constexpr int64_t kPersistMaxRows = 24 * 24 * 24;
+constexpr int64_t kPersistMaxRows = 24 * 24 * 24;    // mixed precision
+constexpr int64_t kPersistMaxRows64 = 19 * 19 * 19;  // float64: one launch per step is faster from 20^3
 constexpr int kPersistMaxGroups = 32;
 constexpr int64_t kBarrierSpins = 1 << 22;
 
@@ -1492,7 +1495,8 @@ static int solve_impl(cfd_csr_t A, const double *b, const double *x0, double tol
     const bool resident = opts.driver == CFD_DRIVER_RESIDENT ||
                           (opts.driver == CFD_DRIVER_AUTO && A->n <= kResMaxRows);
     bool persist = !resident && (opts.driver == CFD_DRIVER_PERSISTENT ||
-                                 (opts.driver == CFD_DRIVER_AUTO && A->n <= kPersistMaxRows));
+                                 (opts.driver == CFD_DRIVER_AUTO &&
+                                  A->n <= (mixed ? kPersistMaxRows : kPersistMaxRows64)));
     if (persist) {
         int coop = 0;
         CFD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, A->device));
