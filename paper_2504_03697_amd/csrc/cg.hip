@@ -524,6 +524,15 @@ __device__ __forceinline__ void a64_final(const SolveArgs &a, const CgState &st,
 // float32 copy: they are small integers, so each float64 product, and the
 // result, is bit-identical to the one with the float64 copy, at 4 B per entry
 // less.  The same holds for every kernel of the solver that reads values.
+__device__ __forceinline__ CgState a64_next(const CgState &st, const Decision &D) {
+    CgState ns = D.ns;
+    ns.mode = MODE_NORMAL;
+    ns.iters = st.iters + 1;
+    ns.pcur = 1 - st.pcur;
+    ns.alpha = 0.0;
+    return ns;
+}
+
 __device__ __forceinline__ CgState a64_body(const SolveArgs &a, const CgState &st, const Decision &D, double *red,
                                             int32_t *s_col, float *s_val) {
     const double *pold = st.pcur ? a.p1 : a.p0;
@@ -568,8 +577,10 @@ __global__ void __launch_bounds__(kBlock) cg_a64(SolveArgs a, int64_t t) {
         if (lead()) *out = D.ns;
         return;
     }
-    const CgState ns = a64_body(a, st, D, red, s_col, s_val);
-    if (lead()) *out = ns;
+    // the next state depends on nothing the sweep computes: published first,
+    // it need not stay live (in scratch) across the sweep
+    if (lead()) *out = a64_next(st, D);
+    (void)a64_body(a, st, D, red, s_col, s_val);
 }
 
 // The solve has ended (mixed): x = 0, or x plus the queued updates, plus the
