@@ -1,7 +1,10 @@
 // One fractional time step on the staggered grid (Sec. 3.1 of the paper):
 // forces -> semi-Lagrangian advection -> (viscosity) -> pressure correction
 // (divergence, Poisson solve, gradient correction).  Every stage is a device
-// kernel; the Poisson solve is the library's CG (cfd_solve).
+// kernel; advection and viscosity are one kernel (advdiff_kernel) writing
+// the step's velocity buffers, which the divergence reads and the
+// correction turns into the state's new velocities; the Poisson solve is
+// the library's CG (cfd_solve).
 //
 // Face layouts (x fastest over each component's own face grid):
 //   u: (nx+1) x ny x nz at (i h, (j+1/2) h, (k+1/2) h)
