@@ -2261,8 +2261,32 @@ __global__ void __launch_bounds__(kBlock) rb_k1(RbArgs a, int64_t t) {
         o.y = (k < a.nb && dir.use_p) ? pold[k] : VT(0);
         return o;
     };
-    csr_stream_rows<float>(a.rp, a.col, a.v32, 0, a.nr, s_col, s_val, own, [&](int64_t p, int rs, int re, VT2 o) {
-        const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, [&](int32_t c) { return dir.w(c - a.nr); });
+    // float64: the tile's black directions (black cell p of red row p) go to
+    // LDS with the slab; black neighbours inside the tile's range come from
+    // there (the same value dir.w forms).  FP64 DIC per iteration 64^3 38.1
+    // -> 26.1 us, 256^3 403.9 -> 393.3; the float32 sweep measured slower with
+    // it (256^3 301.8 -> 334.8 us), so it gathers every neighbour.
+    __shared__ VT s_w[MIXED ? 1 : kBlock];
+    int64_t w0 = 0;
+    int wn = 0;
+    auto stage = [&](int64_t r0, int nr, const VT2 &o) {
+        if constexpr (!MIXED) {
+            w0 = r0;
+            wn = (int)(a.nb - r0 < nr ? (a.nb - r0 > 0 ? a.nb - r0 : 0) : nr);
+            if ((int)threadIdx.x < wn) s_w[threadIdx.x] = dir.use_p ? (VT)fma(dir.cf, o.y, o.x) : o.x;
+        }
+    };
+    auto wl = [&](int32_t c) -> VT {
+        const int64_t k = (int64_t)c - a.nr;
+        if constexpr (!MIXED) {
+            const uint32_t d = (uint32_t)(k - w0);
+            if (d < (uint32_t)wn) return s_w[d];
+        }
+        return dir.w(k);
+    };
+    csr_stream_rows_staged<float>(a.rp, a.col, a.v32, 0, a.nr, s_col, s_val, own, stage,
+                                  [&](int64_t p, int rs, int re, VT2 o) {
+        const VT acc = rb_offdiag<VT>(s_col, s_val, rs, re, wl);
         y[p] = acc / (VT)s_val[rs];
         if (p < a.nb) {
             const VT wk = dir.use_p ? (VT)fma(dir.cf, o.y, o.x) : o.x;

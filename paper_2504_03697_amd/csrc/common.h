@@ -380,11 +380,14 @@ struct SlabStream {
 // tile's slab is in LDS, body(i, rs, re, v) runs for every row i of the tile
 // owned by this thread (one row per thread), with [rs, re) the row's entries
 // in s_col/s_val and v = pre(i).  The call is workgroup-uniform; every row
-// holds at least one entry.
-template <class VT, int B = kBlock, class Pre, class Body>
-__device__ inline void csr_stream_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                      const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
-                                      int32_t *s_col, VT *s_val, Pre &&pre, Body &&body) {
+// holds at least one entry.  stage(r0, nr, v) runs in every thread as each
+// tile's slab goes to LDS, before the barrier that publishes it (v = pre of
+// the thread's row of that tile; rows past its end see the last row's), so
+// values it stores in LDS are there for the tile's bodies.
+template <class VT, int B = kBlock, class Pre, class Stage, class Body>
+__device__ inline void csr_stream_rows_staged(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                             const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
+                                             int32_t *s_col, VT *s_val, Pre &&pre, Stage &&stage, Body &&body) {
     using T = decltype(pre(int64_t(0)));
     const int64_t rows = row_end - row_begin;
     const int64_t ntiles = (rows + B - 1) / B;
@@ -411,6 +414,7 @@ __device__ inline void csr_stream_rows(const int32_t *__restrict__ rp, const int
         int b0, b1;
         P.bounds(b0, b1);
         P.commit(s_col, s_val);
+        stage(r0, nr, cur);
         __syncthreads();
         // After the last tile the fetch re-reads the current tile's first
         // vector, so every iteration issues the same loads.
@@ -423,6 +427,14 @@ __device__ inline void csr_stream_rows(const int32_t *__restrict__ rp, const int
         if (tid < nr) body(r0 + tid, rs, re, cur);
         __syncthreads();
     }
+}
+
+template <class VT, int B = kBlock, class Pre, class Body>
+__device__ inline void csr_stream_rows(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                      const VT *__restrict__ val, int64_t row_begin, int64_t row_end,
+                                      int32_t *s_col, VT *s_val, Pre &&pre, Body &&body) {
+    csr_stream_rows_staged<VT, B>(rp, col, val, row_begin, row_end, s_col, s_val, pre,
+                                  [](int64_t, int, const auto &) {}, body);
 }
 
 // row_product with all gathers issued before the first multiply-add: the
