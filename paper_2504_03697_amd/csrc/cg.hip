@@ -543,11 +543,32 @@ __device__ __forceinline__ CgState a64_body(const SolveArgs &a, const CgState &s
     const double beta = D.beta;
     double pq = 0.0;
     auto wg = [&](int32_t j) -> double { return normal ? fma(beta, pold[j], a.r[j]) : a.r[j]; };
-    // the streamed sweep: 3 % faster here than csr_sweep (256^3), no spills
-    auto none = [](int64_t) { return 0; };
-    csr_stream_rows<float>(a.rp, a.col, a.v32, 0, a.n, s_col, s_val, none, [&](int64_t i, int rs, int re, int) {
-        const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, wg), wg);
-        const double wi = wg((int32_t)i);
+    // the streamed sweep: 3 % faster here than csr_sweep (256^3), no spills.
+    // Each row's direction w_i is formed from its r and p_old, loaded a tile
+    // ahead, and staged in LDS with the slab; the row products take the
+    // neighbours inside the tile from there (the same value wg forms).
+    __shared__ double s_w[kBlock];
+    int64_t w0 = 0;
+    int wn = 0;
+    auto own = [&](int64_t i) -> f64x2 {
+        f64x2 o;
+        o.x = a.r[i];
+        o.y = normal ? pold[i] : 0.0;
+        return o;
+    };
+    auto stage = [&](int64_t r0, int nr, const f64x2 &o) {
+        w0 = r0;
+        wn = nr;
+        if ((int)threadIdx.x < nr) s_w[threadIdx.x] = normal ? fma(beta, o.y, o.x) : o.x;
+    };
+    auto wl = [&](int32_t j) -> double {
+        const uint32_t d = (uint32_t)((int64_t)j - w0);
+        return d < (uint32_t)wn ? s_w[d] : wg(j);
+    };
+    csr_stream_rows_staged<float>(a.rp, a.col, a.v32, 0, a.n, s_col, s_val, own, stage,
+                                  [&](int64_t i, int rs, int re, f64x2 o) {
+        const double acc = neu_fix(a, i, row_product<double>(s_col, s_val, rs, re, wl), wg);
+        const double wi = normal ? fma(beta, o.y, o.x) : o.x;
         if (fold && alpha != 0.0) store_stream(a.x + i, folded64(a, i, alpha, pold));
         store_stream(pnew + i, wi);
         store_stream(a.q + i, acc);
