@@ -62,3 +62,26 @@ def test_committed_profile_matches_the_kernel_sources():
     assert t is not None, "re-profile cg_a32 (profiles/cg_a32_poisson_256.md) for the current sources"
     alg = bench.a_kernel_bytes(n**3, 7 * n**3 - 6 * n**2 - 6, True)
     assert alg <= t <= 1.2 * alg
+
+
+def test_step_workload_options():
+    """--workload takes solve (the headline) or step (cavity steps for the
+    time-step kernels); the step workload is one GPU too."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "other"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "invalid choice" in r.stderr
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--workload", "step", "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "single GPU" in r.stderr
+
+
+def test_step_profile_face_count():
+    """The step-kernel profile's faces: 3 n^2 (n+1) at 256^3, the count its
+    algorithmic bytes are built from (16 B per face for advection +
+    viscosity, 8 B per face + 8 B per cell for the divergence)."""
+    text = open(os.path.join(ROOT, "profiles", "step_kernels_256.md")).read()
+    n = 256
+    faces = 3 * n * n * (n + 1)
+    assert f"{faces:,}" in text
+    assert f"| {8 * faces / 1e6:.1f} + {8 * faces / 1e6:.1f} |" in text
+    assert f"| {8 * faces / 1e6:.1f} + {8 * n**3 / 1e6:.1f} |" in text
