@@ -239,3 +239,23 @@ def test_advection_of_linear_fields_is_exact(dims):
         assert np.all(np.abs(f[c][m] - expect[m]) > 1e-6)
         checked += int(m.sum())
     assert checked > 500
+
+
+def test_random_flow_generator():
+    """synth.random_flow: the three face arrays in their sizes, values in
+    [-amp, amp], wall-normal faces zero, the same arrays for the same seed."""
+    import synth
+    dims = (5, 4, 3)
+    nx, ny, nz = dims
+    u, v, w = synth.random_flow(dims, 11, amp=0.5)
+    su, sv, sw, _ = oracle.face_shapes(dims)
+    assert (u.size, v.size, w.size) == (su, sv, sw)
+    for a in (u, v, w):
+        assert np.abs(a).max() <= 0.5 and np.abs(a).max() > 0
+    U, V, W = u.reshape(nz, ny, nx + 1), v.reshape(nz, ny + 1, nx), w.reshape(nz + 1, ny, nx)
+    assert not U[:, :, 0].any() and not U[:, :, nx].any()
+    assert not V[:, 0, :].any() and not V[:, ny, :].any()
+    assert not W[0].any() and not W[nz].any()
+    u2, v2, w2 = synth.random_flow(dims, 11, amp=0.5)
+    assert np.array_equal(u, u2) and np.array_equal(v, v2) and np.array_equal(w, w2)
+    assert not np.array_equal(u, synth.random_flow(dims, 12, amp=0.5)[0])
